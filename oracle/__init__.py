@@ -1,0 +1,148 @@
+"""CPU oracle for perm(A) mod 3 -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the GPU library
+(``paper_2407_20205_amd``) and never imports it.
+
+Two independent definitions live here:
+
+* ``brute_perm`` -- the permanent by its definition, eq. (1): a sum over all
+  n! permutations of products of entries, in exact Python integers.  Used for
+  n <= 8.
+* the C oracle (``perm3_oracle.c``) -- Ryser's identity, eq. (2), walked in
+  reflected-binary Gray-code order with UNPACKED centred residues (Section 3
+  with its cmod3 reduction), threaded over blocks of consecutive Gray indices
+  as in Section 3.1.  It returns exact partial tallies T(a, b) and perm mod 3.
+
+Inputs are n x n uint8 matrices with entries in {0, 1, 2}; 2 stands for -1.
+"""
+from __future__ import annotations
+
+import ctypes
+import itertools
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "perm3_oracle.c")
+_LIB = os.path.join(_HERE, "libperm3_oracle.so")
+
+MAX_N = 63
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc into ``oracle/libperm3_oracle.so``."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", "-O2", "-fPIC", "-shared", "-pthread", "-Wall",
+                        "-Wextra", "-o", tmp, _SRC], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    """The loaded C oracle; built first only if no built copy exists."""
+    global _lib
+    if _lib is None:
+        path = build(force=False)
+        L = ctypes.CDLL(path)
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        L.oracle_term.argtypes = [u8p, ctypes.c_int, ctypes.c_uint64]
+        L.oracle_term.restype = ctypes.c_int
+        L.oracle_range_tally.argtypes = [u8p, ctypes.c_int, ctypes.c_uint64,
+                                         ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+        L.oracle_range_tally.restype = ctypes.c_int64
+        L.oracle_range_tally_mt.argtypes = [u8p, ctypes.c_int, ctypes.c_uint64,
+                                            ctypes.c_uint64, ctypes.c_int,
+                                            ctypes.POINTER(ctypes.c_int)]
+        L.oracle_range_tally_mt.restype = ctypes.c_int64
+        L.oracle_perm_mod3.argtypes = [u8p, ctypes.c_int, ctypes.c_int]
+        L.oracle_perm_mod3.restype = ctypes.c_int
+        L.oracle_count_by_value.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
+        L.oracle_count_by_value.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _mat(A) -> tuple[np.ndarray, int]:
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.uint8))
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("square matrix expected")
+    return A, A.shape[0]
+
+
+def _ptr(A: np.ndarray):
+    return A.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return max(1, os.cpu_count() or 1)
+
+
+def term(A, i: int) -> int:
+    """One Ryser term for Gray index i, formed from scratch: (-1)^|S| prod_col sum_{k in S} A[k][col], S = g(i)."""
+    A, n = _mat(A)
+    return lib().oracle_term(_ptr(A), n, i)
+
+
+def range_tally(A, a: int, b: int, threads: int | None = None) -> int:
+    """Exact T(a, b) = sum of Ryser terms over Gray indices a <= i < b."""
+    A, n = _mat(A)
+    ok = ctypes.c_int(0)
+    if threads is None or threads <= 1:
+        v = lib().oracle_range_tally(_ptr(A), n, a, b, ctypes.byref(ok))
+    else:
+        v = lib().oracle_range_tally_mt(_ptr(A), n, a, b, threads, ctypes.byref(ok))
+    if not ok.value:
+        raise ValueError("invalid matrix or range")
+    return int(v)
+
+
+def perm_mod3(A, threads: int | None = None) -> int:
+    """perm(A) mod 3 in {0, 1, 2} through Ryser + Gray code on unpacked residues."""
+    A, n = _mat(A)
+    r = lib().oracle_perm_mod3(_ptr(A), n, threads or default_threads())
+    if r < 0:
+        raise ValueError("invalid matrix")
+    return r
+
+
+def count_by_value(n: int) -> tuple[int, int, int]:
+    """Over all 3^(n*n) matrices (n <= 4): how many have perm 0, 1 and -1."""
+    c = (ctypes.c_uint64 * 3)()
+    if lib().oracle_count_by_value(n, c) != 0:
+        raise ValueError("n must be in 1..4")
+    return int(c[0]), int(c[1]), int(c[2])
+
+
+def signed(A) -> list[list[int]]:
+    """Entries as integers in {-1, 0, 1} (2 read as -1)."""
+    A, n = _mat(A)
+    return [[-1 if int(x) == 2 else int(x) for x in row] for row in A]
+
+
+def brute_perm(A) -> int:
+    """perm(A) over the integers by eq. (1): sum over sigma in S_n of prod_i a_{i, sigma(i)}."""
+    M = signed(A)
+    n = len(M)
+    total = 0
+    for sigma in itertools.permutations(range(n)):
+        p = 1
+        for i in range(n):
+            p *= M[i][sigma[i]]
+            if p == 0:
+                break
+        total += p
+    return total
+
+
+def brute_perm_mod3(A) -> int:
+    return brute_perm(A) % 3

@@ -1,0 +1,235 @@
+/*
+ * CPU oracle for perm(A) mod 3 -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Only the test suite, the smoke check and the benchmark's CPU-baseline leg
+ * load this code.  It shares nothing with the GPU library: no headers, no
+ * helpers, no tables.  It is deliberately plain and slow.
+ *
+ * What it computes (Scheinerman, "Fast computation of permanents over F_3
+ * via F_2 arithmetic"):
+ *
+ *   perm(A) = sum over permutations sigma of prod_i a_{i,sigma(i)}   (eq. 1)
+ *
+ * reached through Ryser's identity (eq. 2), read over ROW subsets S as the
+ * paper's own code does (eq. 2 printed over column subsets is the same
+ * number because perm(A) = perm(A^T)):
+ *
+ *   perm(A) = (-1)^n * sum_S (-1)^|S| * prod_cols ( sum_{k in S} A[k][col] ).
+ *
+ * The subsets are visited in reflected-binary Gray-code order (Section 3,
+ * footnote on the RBC): Gray index i has state g(i) = i xor (i >> 1), and the
+ * step into index i flips row ctz(i).  A row is subtracted when it leaves
+ * the subset (its bit is set in the previous state) and added when it
+ * enters.  Elements are kept UNPACKED, one int per column, reduced to the
+ * centred residues {-1, 0, 1} after every update (the cmod3 of Section 3),
+ * so every column product is in {-1, 0, 1}.
+ *
+ * Matrix entries are bytes in {0,1,2}; 2 is read as -1.  Results are in
+ * {0,1,2}.  A partial tally T(a,b) is the exact signed integer
+ *     T(a,b) = sum_{a <= i < b} (-1)^|g(i)| * prod_cols v_col(g(i))
+ * with v(S) the centred column sums of the rows in S; T is additive over
+ * ranges and perm(A) mod 3 = (-1)^n T(0, 2^n) mod 3.  A block of
+ * consecutive Gray indices starts by jumping straight to state g(a)
+ * (Section 3.1).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <pthread.h>
+
+#define ORACLE_MAX_N 63
+
+/* cmod3 (Section 3): mod(x,3) mapped to {-1,0,1}. */
+static int centred_mod3(int64_t x)
+{
+    int64_t a = x % 3;
+    if (a < 0) a += 3;
+    return a == 2 ? -1 : (int)a;
+}
+
+/* Entry of A as an element of F_3 in {-1,0,1}. */
+static int entry(const uint8_t *A, int n, int row, int col)
+{
+    return A[row * n + col] == 2 ? -1 : (int)A[row * n + col];
+}
+
+static int popcount64(uint64_t x)
+{
+    int c = 0;
+    while (x) { c += (int)(x & 1u); x >>= 1; }
+    return c;
+}
+
+static int trailing_zeros64(uint64_t x)
+{
+    int t = 0;
+    while (!(x & 1u)) { x >>= 1; ++t; }
+    return t;
+}
+
+/* Reject anything the definition does not cover. */
+static int valid_input(const uint8_t *A, int n)
+{
+    if (n < 0 || n > ORACLE_MAX_N) return 0;
+    if (n > 0 && A == NULL) return 0;
+    for (int k = 0; k < n * n; ++k)
+        if (A[k] > 2) return 0;
+    return 1;
+}
+
+/*
+ * One Ryser term by its definition, no Gray walk: the subset is g(i), the
+ * column sums are formed from scratch, and the sign is (-1)^|S| counted on
+ * the subset itself.
+ */
+int oracle_term(const uint8_t *A, int n, uint64_t i)
+{
+    if (!valid_input(A, n)) return 0;
+    uint64_t S = i ^ (i >> 1);
+    int prod = 1;
+    for (int col = 0; col < n; ++col) {
+        int64_t sum = 0;
+        for (int k = 0; k < n; ++k)
+            if ((S >> k) & 1u) sum += entry(A, n, k, col);
+        prod *= centred_mod3(sum);
+    }
+    return (popcount64(S) & 1) ? -prod : prod;
+}
+
+/*
+ * T(a,b) by a Gray-code walk over unpacked centred residues, the way the
+ * paper's plain Ryser routine walks (with its cmod3 reduction).  Returns 0 and
+ * sets *ok = 0 on invalid input or a range outside [0, 2^n].
+ */
+int64_t oracle_range_tally(const uint8_t *A, int n, uint64_t a, uint64_t b, int *ok)
+{
+    if (ok) *ok = 0;
+    if (!valid_input(A, n)) return 0;
+    uint64_t total = (uint64_t)1 << n;
+    if (a > b || b > total) return 0;
+    if (ok) *ok = 1;
+    if (a == b) return 0;
+
+    /* the matrix as centred residues, E[k][col] in {-1,0,1} */
+    int E[ORACLE_MAX_N][ORACLE_MAX_N];
+    for (int k = 0; k < n; ++k)
+        for (int col = 0; col < n; ++col)
+            E[k][col] = entry(A, n, k, col);
+
+    int v[ORACLE_MAX_N];
+    /* jump to state g(a): add every row whose bit is set */
+    uint64_t x = a ^ (a >> 1);
+    for (int col = 0; col < n; ++col) {
+        int64_t sum = 0;
+        for (int k = 0; k < n; ++k)
+            if ((x >> k) & 1u) sum += E[k][col];
+        v[col] = centred_mod3(sum);
+    }
+
+    int64_t s = 0;
+    for (uint64_t i = a; i < b; ++i) {
+        if (i > a) {
+            int t = trailing_zeros64(i);
+            int leaving = (int)((x >> t) & 1u);   /* row t is in the subset: remove it */
+            x ^= (uint64_t)1 << t;
+            for (int col = 0; col < n; ++col)
+                v[col] = centred_mod3(leaving ? v[col] - E[t][col] : v[col] + E[t][col]);
+        }
+        int prod = 1;
+        for (int col = 0; col < n; ++col) prod *= v[col];
+        if (popcount64(x) & 1) s -= prod; else s += prod;
+    }
+    return s;
+}
+
+/* ------------------------------------------------------------------ */
+/* Threaded whole-range tally: the paper's parallel scheme (Section 3.1) of
+ * independent blocks of consecutive Gray indices, partial sums added.     */
+
+typedef struct {
+    const uint8_t *A;
+    int n;
+    uint64_t a, b;
+    int64_t out;
+    int ok;
+} oracle_job;
+
+static void *oracle_job_run(void *p)
+{
+    oracle_job *j = (oracle_job *)p;
+    j->out = oracle_range_tally(j->A, j->n, j->a, j->b, &j->ok);
+    return NULL;
+}
+
+int64_t oracle_range_tally_mt(const uint8_t *A, int n, uint64_t a, uint64_t b,
+                              int nthreads, int *ok)
+{
+    if (ok) *ok = 0;
+    if (!valid_input(A, n)) return 0;
+    uint64_t total = (uint64_t)1 << n;
+    if (a > b || b > total) return 0;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    uint64_t len = b - a;
+    if (len < (uint64_t)nthreads * 4096u) nthreads = 1;
+
+    oracle_job jobs[256];
+    pthread_t th[256];
+    for (int k = 0; k < nthreads; ++k) {
+        jobs[k].A = A; jobs[k].n = n;
+        jobs[k].a = a + len * (uint64_t)k / (uint64_t)nthreads;
+        jobs[k].b = a + len * (uint64_t)(k + 1) / (uint64_t)nthreads;
+        jobs[k].out = 0; jobs[k].ok = 0;
+    }
+    int started = 0;
+    for (int k = 1; k < nthreads; ++k) {
+        if (pthread_create(&th[k], NULL, oracle_job_run, &jobs[k]) != 0) break;
+        started = k;
+    }
+    oracle_job_run(&jobs[0]);
+    for (int k = started + 1; k < nthreads; ++k)
+        oracle_job_run(&jobs[k]);   /* threads that failed to start run inline */
+    for (int k = 1; k <= started; ++k) pthread_join(th[k], NULL);
+
+    int64_t s = 0;
+    int all_ok = 1;
+    for (int k = 0; k < nthreads; ++k) { s += jobs[k].out; all_ok &= jobs[k].ok; }
+    if (ok) *ok = all_ok;
+    return s;
+}
+
+/* perm(A) mod 3 in {0,1,2}; -1 on invalid input.  For n = 0 the only subset is
+ * the empty one and its empty product is 1, so perm of the 0x0 matrix is 1. */
+int oracle_perm_mod3(const uint8_t *A, int n, int nthreads)
+{
+    if (!valid_input(A, n)) return -1;
+    int ok = 0;
+    int64_t T = oracle_range_tally_mt(A, n, 0, (uint64_t)1 << n, nthreads, &ok);
+    if (!ok) return -1;
+    int64_t p = (n & 1) ? -T : T;          /* the (-1)^n of eq. 2 */
+    int r = centred_mod3(p);
+    return r < 0 ? 2 : r;
+}
+
+/*
+ * z(n) of Section 4: how many of the 3^(n*n) matrices over F_3 have
+ * permanent 0, by visiting every one of them.  n <= 4 (3^16 matrices).
+ * Also returns the counts of permanent 1 and permanent -1 (= 2).
+ */
+int oracle_count_by_value(int n, uint64_t counts[3])
+{
+    counts[0] = counts[1] = counts[2] = 0;
+    if (n < 1 || n > 4) return -1;
+    int cells = n * n;
+    uint8_t A[16];
+    memset(A, 0, sizeof A);
+    for (;;) {
+        int r = oracle_perm_mod3(A, n, 1);
+        counts[r] += 1;
+        int k = 0;                        /* next matrix: base-3 odometer */
+        while (k < cells && A[k] == 2) { A[k] = 0; ++k; }
+        if (k == cells) break;
+        A[k] += 1;
+    }
+    return 0;
+}

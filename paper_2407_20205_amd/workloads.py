@@ -1,0 +1,185 @@
+"""Seeded synthetic inputs for perm(A) mod 3.
+
+This module only draws random numbers and arranges them into matrices,
+index lists and arrival times.  It holds none of the method's arithmetic and
+imports nothing from the rest of the package, so the GPU path, the tests and
+the CPU oracle can all take their inputs from it.
+
+Every generator uses numpy ``Generator(PCG64(seed))``.  Matrices are n x n,
+uint8, row-major, entries in {0, 1, 2} where 2 stands for -1 in F_3.  The
+paper times random matrices with iid entries in {-1, 0, 1} (Section 3,
+Table 2) and samples uniform random matrices for its Monte Carlo study
+(Section 4); the uniform draws below are those distributions.
+"""
+from __future__ import annotations
+
+import hashlib
+from dataclasses import dataclass, field
+
+import numpy as np
+
+# seeds of the five standard workloads
+SEED_SINGLE_20 = 1
+SEED_SINGLE_36 = 2
+SEED_BATCH = 3
+SEED_SERVE = 4
+SEED_LARGE = 5
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def uniform_matrix(n: int, seed: int) -> np.ndarray:
+    """One n x n matrix with iid entries uniform on {0, 1, 2}."""
+    return rng(seed).integers(0, 3, size=(n, n), dtype=np.uint8)
+
+
+def sparse_matrix(n: int, g: np.random.Generator, p=(0.6, 0.2, 0.2)) -> np.ndarray:
+    """Entries iid with P(0), P(1), P(2) = p."""
+    return g.choice(np.arange(3, dtype=np.uint8), size=(n, n), p=list(p)).astype(np.uint8)
+
+
+def sha256(*arrays) -> str:
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
+
+
+def single_20() -> np.ndarray:
+    """One 20 x 20 uniform matrix (2^20 Gray indices)."""
+    return uniform_matrix(20, SEED_SINGLE_20)
+
+
+def single_36() -> np.ndarray:
+    """One 36 x 36 uniform matrix (2^36 Gray indices)."""
+    return uniform_matrix(36, SEED_SINGLE_36)
+
+
+def sample_chunks(n: int, seed: int, count: int = 64, log_len: int = 24,
+                  unaligned: int = 8) -> list[tuple[int, int]]:
+    """Seed-chosen Gray index ranges [a, b) of a 2^n range for spot checks.
+
+    ``count - unaligned`` aligned chunks of length 2^log_len are drawn from the
+    2^(n - log_len) chunk slots; the first and last slot are always among them
+    and so is at least one odd slot.  ``unaligned`` further ranges start and
+    end at arbitrary indices (length up to 2^log_len).
+    """
+    g = rng(seed)
+    slots = 1 << (n - log_len)
+    L = 1 << log_len
+    n_al = max(0, count - unaligned)
+    chosen = [0, slots - 1]
+    if slots > 2:
+        chosen.append(int(g.integers(0, slots // 2)) * 2 + 1)
+    while len(chosen) < min(n_al, slots):
+        c = int(g.integers(0, slots))
+        if c not in chosen:
+            chosen.append(c)
+    out = [(c * L, (c + 1) * L) for c in chosen[:n_al]]
+    total = 1 << n
+    for _ in range(unaligned):
+        a = int(g.integers(0, total - 1))
+        ln = int(g.integers(1, L + 1))
+        out.append((a, min(total, a + ln)))
+    return out
+
+
+@dataclass
+class Batch:
+    ns: np.ndarray                  # int32[count]
+    mats: list                      # list of uint8 (n, n) arrays
+    seed: int = SEED_BATCH
+
+    @property
+    def count(self) -> int:
+        return len(self.mats)
+
+    def flat(self) -> tuple[np.ndarray, np.ndarray]:
+        """All matrices concatenated row-major, and the byte offset of each."""
+        offs = np.zeros(self.count + 1, dtype=np.int64)
+        offs[1:] = np.cumsum(self.ns.astype(np.int64) ** 2)
+        buf = np.concatenate([m.reshape(-1) for m in self.mats]) if self.count else np.zeros(0, np.uint8)
+        return buf, offs
+
+
+def batch_uniform(count: int = 8192, n_lo: int = 12, n_hi: int = 28,
+                  seed: int = SEED_BATCH) -> Batch:
+    """``count`` matrices, n uniform on [n_lo, n_hi], entries uniform; n values drawn first."""
+    g = rng(seed)
+    ns = g.integers(n_lo, n_hi + 1, size=count).astype(np.int32)
+    mats = [g.integers(0, 3, size=(int(n), int(n)), dtype=np.uint8) for n in ns]
+    return Batch(ns=ns, mats=mats, seed=seed)
+
+
+def large_sparse(seed: int = SEED_LARGE, n_big: int = 44, n_sparse: int = 40,
+                 count_sparse: int = 64) -> tuple[np.ndarray, Batch]:
+    """One n_big x n_big uniform matrix plus ``count_sparse`` n_sparse matrices with P(0) = 0.6."""
+    g = rng(seed)
+    big = g.integers(0, 3, size=(n_big, n_big), dtype=np.uint8)
+    mats = [sparse_matrix(n_sparse, g) for _ in range(count_sparse)]
+    return big, Batch(ns=np.full(count_sparse, n_sparse, np.int32), mats=mats, seed=seed)
+
+
+def serve_n_weights(n_lo: int = 8, n_hi: int = 40, ratio: float = 1.15) -> tuple[np.ndarray, np.ndarray]:
+    ns = np.arange(n_lo, n_hi + 1)
+    w = ratio ** (-(ns - n_lo).astype(np.float64))
+    return ns, w / w.sum()
+
+
+@dataclass
+class ServeTrace:
+    ns: np.ndarray                  # int32[count]
+    mats: list
+    arrival_s: np.ndarray           # float64[count], seconds from the start, nondecreasing
+    rate: float
+    seed: int = SEED_SERVE
+    meta: dict = field(default_factory=dict)
+
+
+def serve_trace(count: int = 20000, rate: float = 1000.0, seed: int = SEED_SERVE,
+                n_lo: int = 8, n_hi: int = 40, ratio: float = 1.15) -> ServeTrace:
+    """Open-loop request stream: n with P(n) proportional to ratio^-(n - n_lo),
+    Poisson arrivals at ``rate`` per second (exponential gaps), uniform entries.
+    Draw order: all n, then all gaps, then the matrices in arrival order."""
+    g = rng(seed)
+    support, p = serve_n_weights(n_lo, n_hi, ratio)
+    ns = g.choice(support, size=count, p=p).astype(np.int32)
+    gaps = g.exponential(1.0 / rate, size=count)
+    arrival = np.cumsum(gaps) - gaps[0]
+    mats = [g.integers(0, 3, size=(int(n), int(n)), dtype=np.uint8) for n in ns]
+    return ServeTrace(ns=ns, mats=mats, arrival_s=arrival, rate=rate, seed=seed)
+
+
+# ---- structured matrices for checks at sizes no enumeration reaches --------
+
+def hidden_triangular(n: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
+    """P U Q with U upper triangular, nonzero diagonal, random P, Q permutations.
+    Returns the matrix and U's diagonal (entries in {1, 2})."""
+    g = rng(seed)
+    U = g.integers(0, 3, size=(n, n), dtype=np.uint8)
+    U = np.triu(U)
+    d = g.integers(1, 3, size=n, dtype=np.uint8)
+    U[np.arange(n), np.arange(n)] = d
+    P = g.permutation(n)
+    Q = g.permutation(n)
+    return np.ascontiguousarray(U[P][:, Q]), d
+
+
+def hidden_block_diagonal(sizes, seed: int) -> tuple[np.ndarray, list]:
+    """A direct sum of uniform blocks of the given sizes, rows and columns shuffled.
+    Returns the matrix and the list of blocks."""
+    g = rng(seed)
+    n = int(sum(sizes))
+    M = np.zeros((n, n), dtype=np.uint8)
+    blocks = []
+    o = 0
+    for s in sizes:
+        B = g.integers(0, 3, size=(s, s), dtype=np.uint8)
+        M[o:o + s, o:o + s] = B
+        blocks.append(B)
+        o += s
+    P = g.permutation(n)
+    Q = g.permutation(n)
+    return np.ascontiguousarray(M[P][:, Q]), blocks

@@ -1,0 +1,105 @@
+"""Planted mistakes in a throwaway copy of the C oracle must be caught by the pins.
+
+Each mutant is a small textual edit of ``oracle/perm3_oracle.c`` compiled with
+gcc into a temporary directory (CPU only); the original oracle is untouched.
+The pins used are the ones in test_oracle.py: brute force eq. (1), the direct
+per-term definition, and closed forms of T(0, 2^n).
+"""
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2407_20205_amd import workloads as W
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "perm3_oracle.c")
+
+MUTANTS = {
+    # the direction convention of the plain-integer listing (add when the row is already in)
+    "direction_swapped": ("leaving ? v[col] - E[t][col] : v[col] + E[t][col]",
+                          "leaving ? v[col] + E[t][col] : v[col] - E[t][col]"),
+    "drop_minus_one_to_the_n": ("int64_t p = (n & 1) ? -T : T;", "int64_t p = T;"),
+    "drop_subset_sign": ("if (popcount64(x) & 1) s -= prod; else s += prod;", "s += prod;"),
+    "sign_from_index_not_state": ("if (popcount64(x) & 1) s -= prod; else s += prod;",
+                                  "if (i & 2) s -= prod; else s += prod;"),
+    "seed_without_gray": ("uint64_t x = a ^ (a >> 1);", "uint64_t x = a;"),
+    "row_off_by_one": ("v[col] - E[t][col] : v[col] + E[t][col]",
+                       "v[col] - E[(t + 1) % n][col] : v[col] + E[(t + 1) % n][col]"),
+    "seed_transposed": ("if ((x >> k) & 1u) sum += E[k][col];", "if ((x >> k) & 1u) sum += E[col][k];"),
+    "skip_first_term": ("        int prod = 1;\n        for (int col = 0; col < n; ++col) prod *= v[col];",
+                        "        int prod = (i == a) ? 0 : 1;\n        for (int col = 0; col < n; ++col) prod *= v[col];"),
+    # (reading 2 as +2 would be no mistake at all: 2 = -1 in F_3)
+    "minus_one_read_as_one": ("return A[row * n + col] == 2 ? -1 : (int)A[row * n + col];",
+                              "return A[row * n + col] == 2 ? 1 : (int)A[row * n + col];"),
+    "product_skips_last_column": ("for (int col = 0; col < n; ++col) prod *= v[col];",
+                                  "for (int col = 0; col + 1 < n; ++col) prod *= v[col];"),
+}
+
+
+def _build(tmp_path, name, old, new):
+    src = open(SRC).read()
+    assert src.count(old) >= 1, name
+    mutated = src.replace(old, new)
+    c = tmp_path / f"{name}.c"
+    so = tmp_path / f"{name}.so"
+    c.write_text(mutated)
+    subprocess.run(["gcc", "-O1", "-fPIC", "-shared", "-pthread", "-o", str(so), str(c)], check=True)
+    L = ctypes.CDLL(str(so))
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    L.oracle_perm_mod3.argtypes = [u8p, ctypes.c_int, ctypes.c_int]
+    L.oracle_perm_mod3.restype = ctypes.c_int
+    L.oracle_term.argtypes = [u8p, ctypes.c_int, ctypes.c_uint64]
+    L.oracle_term.restype = ctypes.c_int
+    L.oracle_range_tally.argtypes = [u8p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                     ctypes.POINTER(ctypes.c_int)]
+    L.oracle_range_tally.restype = ctypes.c_int64
+    return L
+
+
+def _p(A):
+    A = np.ascontiguousarray(A, dtype=np.uint8)
+    return A, A.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def pins_pass(L) -> bool:
+    ok = ctypes.c_int(0)
+    # brute force eq. (1)
+    for n in range(1, 7):
+        for s in range(6):
+            A, p = _p(W.uniform_matrix(n, 5000 + 10 * n + s))
+            if L.oracle_perm_mod3(p, n, 1) != oracle.brute_perm_mod3(A):
+                return False
+    # Gray walk vs per-term definition on every range start
+    A, p = _p(W.uniform_matrix(5, 77))
+    terms = [0] * 32
+    for i in range(32):
+        terms[i] = L.oracle_term(p, 5, i)
+    for a in range(32):
+        if L.oracle_range_tally(p, 5, a, 32, ctypes.byref(ok)) != sum(terms[a:]):
+            return False
+    # closed forms: T(0,2^n) of I_n is (-1)^n; of J_n is sum_k C(n,k) (-1)^k c(k)^n
+    for n in range(1, 9):
+        _, pI = _p(np.eye(n))
+        if L.oracle_range_tally(pI, n, 0, 1 << n, ctypes.byref(ok)) != (-1) ** n:
+            return False
+        _, pJ = _p(np.ones((n, n)))
+        expect = sum(math.comb(n, k) * (-1) ** k * (((k + 1) % 3) - 1) ** n for k in range(n + 1))
+        if L.oracle_range_tally(pJ, n, 0, 1 << n, ctypes.byref(ok)) != expect:
+            return False
+    return True
+
+
+def test_unmutated_oracle_passes_pins(tmp_path):
+    L = _build(tmp_path, "original", "#include <stdint.h>", "#include <stdint.h>")
+    assert pins_pass(L)
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(tmp_path, name):
+    old, new = MUTANTS[name]
+    L = _build(tmp_path, name, old, new)
+    assert not pins_pass(L), f"planted mistake {name} slipped through the pins"
