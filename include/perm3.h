@@ -1,0 +1,247 @@
+/*
+ * perm3 -- permanents over F_3 on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libperm3.so.  Everything here is plain C: integers, pointers and
+ * sizes.  Pointers marked "host" are ordinary CPU memory; pointers marked
+ * "device" are HIP device allocations (for example torch tensors on cuda:0)
+ * on the library's current device.  The library never frees caller memory.
+ *
+ * The method (Scheinerman, "Fast computation of permanents over F_3 via F_2
+ * arithmetic"):
+ *   - perm(A) by Ryser's identity, eq. (2), summed over row subsets visited in
+ *     reflected-binary Gray-code order, so that consecutive subsets differ by
+ *     one row (Section 3 and its RBC footnote);
+ *   - each length-n vector over F_3 is held "bipedally" as two F_2^n words
+ *     (mag, sgn) under the map phi of Section 2: 0 -> (0,0), 1 -> (1,0),
+ *     -1 -> (1,1), with (0,1) a second legal zero (Definition 2.1);
+ *   - a row is added or subtracted with the and/or/xor formulas of
+ *     Theorem 2.1; a subset's column product is non-zero exactly when every
+ *     mag bit is set, and then equals (-1)^popcount(sgn) (Section 3);
+ *   - independent blocks of consecutive Gray indices are started by jumping
+ *     straight to Gray state i xor (i >> 1) (Section 3.1).
+ *
+ * Conventions shared by every entry point:
+ *   - A matrix is n x n, row-major, one byte per entry, entries in {0,1,2};
+ *     the byte 2 is the element -1 of F_3.
+ *   - 0 <= n <= PERM_MAX_N (63).  perm of the 0 x 0 matrix is 1.
+ *   - Results are bytes in {0,1,2} (2 is -1).
+ *   - Every call returns an int32_t status: PERM_OK (0) or a negative code
+ *     below.  perm_strerror() names a code; perm_last_error() gives the
+ *     calling thread's last message (for PERM_EDEVICE, the HIP error).
+ *   - Calls are thread-safe; calls into one device context are serialised.
+ *     The library lazily creates, per device, a context holding a HIP stream,
+ *     work buffers, cached HIP graphs and the kernel tuning table.
+ */
+#ifndef PERM3_H
+#define PERM3_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PERM_MAX_N 63
+
+/* status codes */
+#define PERM_OK        0
+#define PERM_EINVAL   (-1)  /* null pointer, n or count out of range, bad range or config  */
+#define PERM_EDOMAIN  (-2)  /* a matrix entry > 2, or a packed plane with a bit >= n set    */
+#define PERM_ENOMEM   (-3)  /* a device or host allocation failed                           */
+#define PERM_EDEVICE  (-4)  /* a HIP runtime error, or no gfx950 device                    */
+#define PERM_EAGAIN   (-5)  /* the server's submission queue is full; retry later           */
+#define PERM_ESTATE   (-6)  /* the object is shut down or busy                              */
+
+/* written by the device-input entry points for a matrix that fails validation */
+#define PERM_RESULT_INVALID 0xFFu
+
+/* --------------------------------------------------------------------------
+ * Single matrix.
+ *
+ * perm_mod3: perm(A) mod 3 (eq. 1), computed by the bipedal Gray-code Ryser
+ * sum (Section 3).  A: host, n*n bytes.  *out: host, one byte in {0,1,2}.
+ * Synchronous.  PERM_EINVAL for n < 0, n > 63, or a null pointer (A may be
+ * null when n == 0); PERM_EDOMAIN if any entry > 2 (then perm_last_error_index()
+ * is the offending byte's offset).
+ */
+int32_t perm_mod3(const uint8_t *A, int32_t n, uint8_t *out);
+
+/*
+ * perm_mod3_range_tally: the exact partial Ryser sum over Gray indices
+ * begin <= i < end (Sections 3 and 3.1):
+ *     T(begin,end) = sum_i (-1)^|g(i)| * prod_cols sum_{k in g(i)} a_{k,col},
+ * with g(i) = i xor (i >> 1) a set of rows, each column sum taken in F_3 as
+ * an integer in {-1,0,1}.  T is additive over ranges, and
+ * perm(A) = (-1)^n * T(0, 2^n) mod 3.  Requires 0 <= begin <= end <= 2^n.
+ * A: host.  *tally: host int64.  Synchronous.
+ */
+int32_t perm_mod3_range_tally(const uint8_t *A, int32_t n, uint64_t begin, uint64_t end,
+                          int64_t *tally);
+
+/* --------------------------------------------------------------------------
+ * Many matrices in one persistent launch.
+ *
+ * perm_mod3_batch: As[k] is a host pointer to the k-th n_k x n_k matrix,
+ * ns: host int32[count], out: host uint8[count].  Synchronous.  The whole
+ * batch is validated before anything runs; on error nothing runs and
+ * perm_last_error_index() is the index of the first bad matrix.
+ * 0 <= count <= PERM_MAX_BATCH.
+ */
+#define PERM_MAX_BATCH (1 << 22)
+int32_t perm_mod3_batch(const uint8_t *const *As, const int32_t *ns, int32_t count,
+                         uint8_t *out);
+
+/*
+ * perm_mod3_batch_dev: device-resident form of perm_mod3_batch.
+ *   mats_dev:  device bytes, matrix k at byte offset offs_dev[k], n_k*n_k bytes
+ *   offs_dev:  device int64[count]
+ *   ns_dev:    device int32[count], each in [0, 63]
+ *   out_dev:   device uint8[count]; a matrix with an entry > 2 or n outside
+ *              [0, 63] gets PERM_RESULT_INVALID and is not computed
+ *   hist_dev:  device uint64[64*3] or NULL; the counts of results 0/1/2 are
+ *              ADDED at hist_dev[3*n + r] (the caller zeroes it)
+ *   stream:    a hipStream_t; or NULL: the library's stream, ordered after
+ *              earlier and before later work on the legacy default stream
+ * Asynchronous on `stream`: all steps (validate, pack with phi, plan, Gray
+ * walk, reduce, finish) run as kernels; the call returns after enqueueing.
+ * The launches of one (pointer, count) signature are captured once into a HIP
+ * graph and replayed afterwards.  Buffers must stay valid until the stream
+ * reaches the call's end.
+ */
+int32_t perm_mod3_batch_dev(const uint8_t *mats_dev, const int64_t *offs_dev,
+                             const int32_t *ns_dev, int32_t count, uint8_t *out_dev,
+                             uint64_t *hist_dev, void *stream);
+
+/*
+ * perm_mod3_batch_packed: as perm_mod3_batch_dev but the matrices are
+ * already bipedal.  planes_dev holds, for the r-th row of matrix k,
+ * planes_dev[2*(row_off_dev[k] + r)] = mag and [.. + 1] = sgn as uint64 words
+ * under phi (Section 2): element j of the row (0-based) is bit n-1-j.  Any
+ * bipedal representation is accepted ((0,1) is a zero).  Bits >= n must be
+ * zero in both words; a matrix violating that gets PERM_RESULT_INVALID.
+ * row_off_dev: device int64[count].  Other arguments as perm_mod3_batch_dev.
+ */
+int32_t perm_mod3_batch_packed(const uint64_t *planes_dev, const int64_t *row_off_dev,
+                                const int32_t *ns_dev, int32_t count, uint8_t *out_dev,
+                                uint64_t *hist_dev, void *stream);
+
+/*
+ * perm_mod3_pack: the map phi of Section 2 applied to each row of A on the host:
+ * planes[2r] = mag, planes[2r+1] = sgn of row r, element j at bit n-1-j
+ * (so the row (1,1,0,-1) packs to mag 0xd, sgn 0x1).  A: host n*n bytes,
+ * planes: host uint64[2n].  PERM_EDOMAIN on an entry > 2.
+ */
+int32_t perm_mod3_pack(const uint8_t *A, int32_t n, uint64_t *planes);
+
+/* --------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching.
+ *
+ * Requests (one matrix each) are admitted into device-resident slots while
+ * the total admitted work (sum of 2^n Gray indices still to visit) stays
+ * within work_budget and a slot is free.  The server repeatedly launches a
+ * "tick": a persistent launch that visits up to `quantum` Gray indices,
+ * split across the admitted requests by the policy; each request's partial
+ * tally stays on the device between ticks, so requests that arrive while
+ * others are running join the next tick.  A request finishes when its last
+ * chunk is visited; the finishing kernel reduces its tally mod 3.
+ */
+typedef struct perm_server perm_server;
+
+typedef struct {
+    int32_t  max_slots;     /* device slots (admitted requests); 1..65536          */
+    int32_t  queue_cap;     /* host submission queue capacity; 1..1<<24            */
+    uint64_t work_budget;   /* max admitted Gray indices still to visit (0 = none) */
+    uint64_t quantum;       /* Gray indices per tick (0 = library default)         */
+    int32_t  policy;        /* PERM_POLICY_*                                      */
+    int32_t  reserved;
+} perm_server_cfg;
+
+#define PERM_POLICY_SRPT 0   /* least remaining work first                         */
+#define PERM_POLICY_FIFO 1   /* admission order; each tick serves the oldest first */
+
+typedef struct {
+    uint64_t tag;           /* the caller's tag from perm_server_submit          */
+    int32_t  status;        /* PERM_OK or an error code for this request         */
+    int32_t  n;
+    uint8_t  result;        /* perm mod 3 in {0,1,2}                              */
+    uint8_t  pad[7];
+    uint64_t t_submit_ns;   /* CLOCK_MONOTONIC times                              */
+    uint64_t t_admit_ns;
+    uint64_t t_done_ns;
+} perm_done;
+
+typedef struct {
+    uint64_t submitted, completed, ticks, tick_indices;
+    uint64_t busy_ns;       /* wall time with at least one tick in flight         */
+    int32_t  active_slots, queued;
+} perm_server_stats;
+
+/* Create a server with its own device context, stream and worker thread. */
+int32_t perm_server_create(const perm_server_cfg *cfg, perm_server **out);
+/* Copy A (host, n*n bytes) into the server; the caller may free A at once.
+ * PERM_EAGAIN when the queue is full, PERM_EDOMAIN/EINVAL for bad input. */
+int32_t perm_server_submit(perm_server *s, const uint8_t *A, int32_t n, uint64_t tag);
+/* Move up to max finished requests into out (host); *got = how many.
+ * Waits up to timeout_us for at least one (0 = do not wait). */
+int32_t perm_server_poll(perm_server *s, perm_done *out, int32_t max, int32_t *got,
+                          int64_t timeout_us);
+int32_t perm_server_stats_get(perm_server *s, perm_server_stats *st);
+/* Finish all admitted and queued work, stop the worker and free everything. */
+int32_t perm_server_destroy(perm_server *s);
+
+/* --------------------------------------------------------------------------
+ * Tuning, timing, device facts.
+ */
+typedef struct {
+    int32_t waves_per_simd;   /* persistent waves per SIMD (1..16)                      */
+    int32_t body_log;         /* log2 of the unrolled Gray steps per block: 4, 5 or 6   */
+    int32_t chunk_log_max;    /* largest per-lane chunk, log2 Gray indices (8..30)      */
+    int32_t tasks_per_wave;   /* target tasks per persistent wave for large matrices    */
+    int32_t direct_max_n;     /* n at or below which every step is tested exactly      */
+    int32_t reserved[3];
+} perm_tuning;
+
+int32_t perm_tuning_get(perm_tuning *t);
+int32_t perm_tuning_set(const perm_tuning *t);
+/* Time candidate tunings on the device on synthetic matrices of size n and
+ * keep the fastest; budget_ms bounds the search.  Writes the winner to *best. */
+int32_t perm_autotune(int32_t n, int32_t budget_ms, perm_tuning *best);
+
+typedef struct {
+    double   hot_kernel_ms;   /* Gray-walk kernel of the last call, HIP events on its stream */
+    double   total_ms;        /* all launches of the last call                          */
+    uint64_t indices;         /* Gray indices visited by the last call                   */
+    int32_t  launches;        /* kernel launches of the last call                        */
+    int32_t  graph_replayed;  /* 1 if the last call replayed a cached HIP graph          */
+} perm_timing;
+
+/* Enable (1) or disable (0) event timing of subsequent calls on this thread's device. */
+int32_t perm_timing_enable(int32_t on);
+int32_t perm_timing_last(perm_timing *t);
+
+typedef struct {
+    int32_t compute_units;
+    int32_t simds_per_cu;
+    int32_t wave_size;
+    int32_t max_clock_khz;
+    char    arch[64];
+} perm_device_info;
+
+int32_t perm_device_info_get(perm_device_info *info);
+
+/* Device self-check of Theorem 2.1: for each of the count inputs
+ * in[4k..4k+3] = (mag1, sgn1, mag2, sgn2) (32-bit words), writes
+ * out[8k..8k+7] = (mag,sgn) of +, -, x, / as computed by the device functions
+ * the kernels use.  in/out: host.  For testing. */
+int32_t perm_bipedal_ops(const uint32_t *in, int32_t count, uint32_t *out);
+
+const char *perm_strerror(int32_t code);
+const char *perm_last_error(void);
+int64_t     perm_last_error_index(void);
+const char *perm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PERM3_H */

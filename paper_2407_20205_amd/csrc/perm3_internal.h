@@ -1,0 +1,125 @@
+// Internal declarations shared by the kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace perm3 {
+
+struct RowW;
+
+enum WalkMode : int32_t {
+    MODE_FAST = 0,     // unrolled fast walk over whole chunks, exact replay of candidate blocks
+    MODE_DIRECT = 1,   // every index tested exactly (small n)
+    MODE_NONE = 2,     // no tasks: n == 0, invalid n, or an empty range
+};
+
+// Per-matrix plan, written by the plan kernel.
+struct MatMeta {
+    int32_t n;
+    int32_t m;          // log2 of the per-lane chunk length
+    int32_t mode;       // WalkMode
+    uint32_t ntasks;    // 64 chunks per task
+    int64_t row_base;   // first RowW of this matrix
+    uint64_t lo, hi;    // Gray index range [lo, hi)
+    uint64_t c_first;   // first chunk index (lo >> m)
+};
+
+// counters[] slots
+enum : int { CNT_QUEUE = 0, CNT_TOTAL_TASKS = 1, CNT_COUNT = 4 };
+
+struct PlanArgs {
+    const int32_t *ns;
+    int32_t count;
+    int32_t use_range;            // 1: matrix 0 walks [range_lo, range_hi) only (count == 1)
+    uint64_t range_lo, range_hi;
+    int32_t body_log, chunk_log_max, direct_max_n, direct_chunk_log_max;
+    int32_t waves_total, tasks_per_wave;
+    MatMeta *meta;
+    int32_t *order;               // [count] matrix index by decreasing n
+    uint32_t *task_start;         // [count + 1] first task of order[p]
+    int64_t *tally;               // [count]
+    uint32_t *done;               // [count]
+    uint8_t *status;              // [count] 0 ok, 1 invalid
+    uint32_t *counters;           // [CNT_COUNT]
+    uint8_t *out;                 // [count]
+    uint64_t *hist;               // [64 * 3] or null
+};
+
+struct PackU8Args {
+    const uint8_t *mats;
+    const int64_t *offs;          // byte offset of each matrix
+    const MatMeta *meta;
+    int32_t count;
+    RowW *rows;
+    uint8_t *status;
+};
+
+struct PackPlanesArgs {
+    const uint64_t *planes;       // {mag, sgn} per row
+    const int64_t *row_off;       // first row of each matrix
+    const MatMeta *meta;
+    int32_t count;
+    RowW *rows;
+    uint8_t *status;
+};
+
+struct WalkArgs {
+    const RowW *rows;
+    const MatMeta *meta;
+    const int32_t *order;
+    const uint32_t *task_start;
+    int32_t count;
+    int64_t *tally;
+    uint32_t *done;
+    const uint8_t *status;
+    uint32_t *counters;
+    uint8_t *out;
+    uint64_t *hist;
+};
+
+// Serving: one tick visits an explicit list of tasks over device-resident slots.
+struct TickTask {
+    int32_t slot;
+    int32_t m;            // chunk log
+    int32_t mode;         // WalkMode (FAST or DIRECT)
+    int32_t nchunks;      // valid chunks in this task (1..64)
+    uint64_t c_first;     // first chunk of this task
+};
+
+struct SlotInfo {
+    int32_t n;
+    int32_t pad;
+    int64_t row_base;
+};
+
+struct TickArgs {
+    const RowW *rows;
+    const SlotInfo *slots;
+    const TickTask *tasks;
+    const uint32_t *ntasks;       // device count of tasks in this tick
+    int64_t *tally;               // [max_slots]
+    uint32_t *queue;              // tick work counter, reset by the finish kernel
+};
+
+struct FinishArgs {
+    const int32_t *fin_slots;     // slots that complete in this tick
+    const uint32_t *nfin;
+    const SlotInfo *slots;
+    int64_t *tally;               // read, then cleared for reuse
+    uint8_t *fin_out;             // result per finishing slot
+    uint32_t *queue;              // cleared for the next tick
+};
+
+hipError_t launch_plan(const PlanArgs &a, hipStream_t st);
+hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st);
+hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st);
+hipError_t launch_walk(const WalkArgs &a, int body_log, int grid_blocks, hipStream_t st);
+hipError_t launch_tick(const TickArgs &a, int body_log, int grid_blocks, hipStream_t st);
+hipError_t launch_finish(const FinishArgs &a, int max_fin, hipStream_t st);
+hipError_t launch_slot_pack(const uint8_t *A, int n, RowW *dst, hipStream_t st);
+hipError_t launch_bipedal_ops(const uint32_t *in, int count, uint32_t *out, hipStream_t st);
+
+constexpr int WALK_BLOCK = 256;   // 4 waves, one per SIMD
+
+}  // namespace perm3

@@ -1,0 +1,506 @@
+// gfx950 kernels for perm(A) mod 3 by the bipedal Gray-code Ryser sum.
+//
+//   k_plan        one workgroup: per-matrix chunk size, task counts, the task
+//                 order (largest n first), row offsets; clears counters.
+//   k_pack_u8     phi of Section 2 on byte matrices, with validation.
+//   k_pack_planes accepts caller-packed (mag, sgn) uint64 planes, validated.
+//   k_walk<UL>    persistent waves pull 64-chunk tasks from an atomic queue,
+//                 walk them (perm3_walk.hpp), reduce each task's tally over the
+//                 wavefront with DPP, add it to the matrix's int64 tally; the
+//                 wave that completes a matrix's last task reduces it mod 3
+//                 (Section 3: s times (-1)^n, then cmod3) and counts it in the
+//                 per-n histogram.
+//   k_tick<UL>    the serving form of k_walk over an explicit task list.
+//   k_finish      serving: reduce finished slots' tallies mod 3.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "perm3_internal.h"
+#include "perm3_walk.hpp"
+
+namespace perm3 {
+
+// ------------------------------------------------------------------ helpers
+
+__device__ __forceinline__ Masks masks_for(int n)
+{
+    const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
+    Masks mk;
+    mk.lo = (uint32_t)full;
+    mk.hi = (uint32_t)(full >> 32);
+    return mk;
+}
+
+// Sum over the 64 lanes of a wavefront: an inclusive scan inside each row of
+// 16 lanes with DPP row shifts, then the four row totals read as scalars.
+// Every lane must be active.
+__device__ __forceinline__ int wave_sum(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
+    return __builtin_amdgcn_readlane(v, 15) + __builtin_amdgcn_readlane(v, 31) +
+           __builtin_amdgcn_readlane(v, 47) + __builtin_amdgcn_readlane(v, 63);
+}
+
+// r = ((-1)^n * T) mod 3 in {0, 1, 2} (2 stands for -1).
+__device__ __forceinline__ uint8_t finish_mod3(int n, long long T)
+{
+    long long p = (n & 1) ? -T : T;
+    long long r = p % 3;
+    if (r < 0) r += 3;
+    return (uint8_t)r;
+}
+
+template <int UL>
+__device__ __forceinline__ void load_static_rows(const RowW *__restrict__ R, StaticRows<UL> &sr)
+{
+#pragma unroll
+    for (int t = 0; t < UL; ++t) {
+        sr.m[t] = R[t].m_lo;
+        sr.s[t] = R[t].s_lo;
+        sr.sn[t] = R[t].sn_lo;
+    }
+}
+
+// Walk one lane's chunk c (chunk length 2^m) clipped to [lo, hi).
+template <int UL>
+__device__ __forceinline__ int walk_lane(const RowW *__restrict__ R, int n, int m, int mode, uint64_t c,
+                                         uint64_t lo, uint64_t hi, const StaticRows<UL> &sr)
+{
+    const Masks mk = masks_for(n);
+    const uint64_t a0 = c << m;
+    const uint64_t e0 = a0 + (1ull << m);
+    const uint64_t a = a0 > lo ? a0 : lo;
+    const uint64_t e = e0 < hi ? e0 : hi;
+    if (a >= e) return 0;
+    if (mode == MODE_FAST && a == a0 && e == e0) return walk_chunk_fast<UL>(R, n, m, c, mk, sr);
+    return n > 32 ? walk_range_direct<true>(R, n, a, e, mk) : walk_range_direct<false>(R, n, a, e, mk);
+}
+
+// ------------------------------------------------------------------ plan
+
+template <typename T>
+__device__ T block_incl_scan_1024(T v, T *sh, T &total)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const T add = tid >= off ? sh[tid - off] : (T)0;
+        __syncthreads();
+        sh[tid] += add;
+        __syncthreads();
+    }
+    total = sh[1023];
+    const T r = sh[tid];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ void range_of(const PlanArgs &a, int n, uint64_t &lo, uint64_t &hi)
+{
+    if (a.use_range) {
+        lo = a.range_lo;
+        hi = a.range_hi;
+    } else {
+        lo = 0;
+        hi = 1ull << n;
+    }
+}
+
+__global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
+{
+    __shared__ double s_dbl[1024];
+    __shared__ uint64_t s_u64[1024];
+    __shared__ uint32_t s_bucket[65];
+    __shared__ uint32_t s_cursor[65];
+    const int tid = threadIdx.x;
+
+    if (tid < 65) s_bucket[tid] = 0;
+    if (tid == 0) a.counters[CNT_QUEUE] = 0;
+    __syncthreads();
+
+    // total work and per-n bucket sizes
+    double w = 0.0;
+    for (int k = tid; k < a.count; k += 1024) {
+        const int n = a.ns[k];
+        const bool valid = n >= 0 && n <= 63;
+        if (valid) {
+            uint64_t lo, hi;
+            range_of(a, n, lo, hi);
+            w += (double)(hi - lo);
+        }
+        atomicAdd(&s_bucket[valid ? n : 64], 1u);
+    }
+    s_dbl[tid] = w;
+    __syncthreads();
+    for (int off = 512; off > 0; off >>= 1) {
+        if (tid < off) s_dbl[tid] += s_dbl[tid + off];
+        __syncthreads();
+    }
+    const double total_work = s_dbl[0];
+    if (tid == 0) {
+        uint32_t off = 0;
+        for (int b = 63; b >= 0; --b) {
+            s_cursor[b] = off;
+            off += s_bucket[b];
+        }
+        s_cursor[64] = off;
+    }
+    __syncthreads();
+
+    // chunk length that gives each persistent wave about tasks_per_wave tasks
+    const double want_tasks = (double)a.waves_total * (double)(a.tasks_per_wave > 0 ? a.tasks_per_wave : 1);
+    const double per_task = total_work / want_tasks;
+    int target_m = 0;
+    if (per_task >= 128.0) {
+        const uint64_t pt = (uint64_t)per_task;
+        target_m = (63 - __builtin_clzll(pt)) - 6;
+    }
+
+    for (int k = tid; k < a.count; k += 1024) {
+        const int n = a.ns[k];
+        const bool valid = n >= 0 && n <= 63;
+        MatMeta mt;
+        mt.n = valid ? n : 0;
+        mt.m = 0;
+        mt.mode = MODE_NONE;
+        mt.ntasks = 0;
+        mt.row_base = 0;
+        mt.lo = 0;
+        mt.hi = 0;
+        mt.c_first = 0;
+        a.tally[k] = 0;
+        a.done[k] = 0;
+        a.status[k] = valid ? 0 : 1;
+        if (!valid) {
+            a.out[k] = 0xFF;
+        } else if (n == 0) {
+            // the empty product: perm of the 0 x 0 matrix is 1
+            a.out[k] = 1;
+            if (a.hist) atomicAdd((unsigned long long *)&a.hist[1], 1ull);
+        } else {
+            uint64_t lo, hi;
+            range_of(a, n, lo, hi);
+            mt.lo = lo;
+            mt.hi = hi;
+            const bool fast_ok = n >= a.body_log + 7 && n > a.direct_max_n;
+            int m;
+            if (fast_ok) {
+                const int mmax = a.chunk_log_max < n - 6 ? a.chunk_log_max : n - 6;
+                m = target_m;
+                if (m > mmax) m = mmax;
+                if (m < a.body_log + 1) m = a.body_log + 1;
+                mt.mode = MODE_FAST;
+            } else {
+                m = n - 6;
+                if (m > a.direct_chunk_log_max) m = a.direct_chunk_log_max;
+                if (m < 0) m = 0;
+                mt.mode = MODE_DIRECT;
+            }
+            mt.m = m;
+            if (hi > lo) {
+                const uint64_t c0 = lo >> m;
+                const uint64_t c1 = (hi - 1) >> m;
+                mt.c_first = c0;
+                mt.ntasks = (uint32_t)((c1 - c0 + 1 + 63) >> 6);
+            } else {
+                mt.mode = MODE_NONE;
+                a.out[k] = finish_mod3(n, 0);
+            }
+        }
+        a.meta[k] = mt;
+        const uint32_t pos = atomicAdd(&s_cursor[valid ? n : 64], 1u);
+        a.order[pos] = k;
+    }
+    __syncthreads();
+
+    // first task of each position in the order
+    uint64_t running = 0;
+    for (int base = 0; base < a.count; base += 1024) {
+        const int p = base + tid;
+        const uint64_t v = p < a.count ? (uint64_t)a.meta[a.order[p]].ntasks : 0;
+        uint64_t tot;
+        const uint64_t incl = block_incl_scan_1024<uint64_t>(v, s_u64, tot);
+        if (p < a.count) a.task_start[p] = (uint32_t)(running + incl - v);
+        running += tot;
+    }
+    if (tid == 0) {
+        a.task_start[a.count] = (uint32_t)running;
+        a.counters[CNT_TOTAL_TASKS] = (uint32_t)running;
+    }
+
+    // row offsets in matrix order
+    uint64_t rrun = 0;
+    for (int base = 0; base < a.count; base += 1024) {
+        const int k = base + tid;
+        const uint64_t v = k < a.count ? (uint64_t)a.meta[k].n : 0;
+        uint64_t tot;
+        const uint64_t incl = block_incl_scan_1024<uint64_t>(v, s_u64, tot);
+        if (k < a.count) a.meta[k].row_base = (int64_t)(rrun + incl - v);
+        rrun += tot;
+    }
+}
+
+// ------------------------------------------------------------------ pack
+
+__device__ __forceinline__ void store_row(RowW *dst, uint64_t mag, uint64_t sgn)
+{
+    RowW r;
+    const uint64_t sn = sgn ^ mag;
+    r.m_lo = (uint32_t)mag;
+    r.s_lo = (uint32_t)sgn;
+    r.sn_lo = (uint32_t)sn;
+    r.pad0 = 0;
+    r.m_hi = (uint32_t)(mag >> 32);
+    r.s_hi = (uint32_t)(sgn >> 32);
+    r.sn_hi = (uint32_t)(sn >> 32);
+    r.pad1 = 0;
+    *dst = r;
+}
+
+// phi (Section 2): mag bit = (a != 0), sgn bit = (a == -1); element j of a
+// row goes to bit n-1-j, so (1,1,0,-1) becomes (0xd, 0x1).
+__global__ void __launch_bounds__(64) k_pack_u8(PackU8Args a)
+{
+    const int k = blockIdx.x;
+    if (k >= a.count) return;
+    const MatMeta mt = a.meta[k];
+    if (mt.mode == MODE_NONE) return;
+    const int n = mt.n;
+    const int r = threadIdx.x;
+    if (r >= n) return;
+    const uint8_t *row = a.mats + a.offs[k] + (int64_t)r * n;
+    uint64_t mag = 0, sgn = 0;
+    bool bad = false;
+    for (int j = 0; j < n; ++j) {
+        const uint8_t v = row[j];
+        const uint64_t bit = 1ull << (n - 1 - j);
+        bad |= v > 2;
+        if (v != 0) mag |= bit;
+        if (v == 2) sgn |= bit;
+    }
+    if (bad) a.status[k] = 1;
+    store_row(a.rows + mt.row_base + r, mag, sgn);
+}
+
+__global__ void __launch_bounds__(64) k_pack_planes(PackPlanesArgs a)
+{
+    const int k = blockIdx.x;
+    if (k >= a.count) return;
+    const MatMeta mt = a.meta[k];
+    if (mt.mode == MODE_NONE) return;
+    const int n = mt.n;
+    const int r = threadIdx.x;
+    if (r >= n) return;
+    const int64_t src = a.row_off[k] + r;
+    const uint64_t mag = a.planes[2 * src];
+    const uint64_t sgn = a.planes[2 * src + 1];
+    const uint64_t high = (n >= 64) ? 0 : ~((1ull << n) - 1ull);
+    if ((mag | sgn) & high) a.status[k] = 1;
+    store_row(a.rows + mt.row_base + r, mag, sgn);
+}
+
+// ------------------------------------------------------------------ walk
+
+template <int UL>
+__global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t total = a.counters[CNT_TOTAL_TASKS];
+    for (;;) {
+        uint32_t tau = 0;
+        if (lane == 0) tau = atomicAdd(&a.counters[CNT_QUEUE], 1u);
+        tau = __builtin_amdgcn_readfirstlane(tau);
+        if (tau >= total) break;
+
+        // position p in the order whose tasks contain tau: the largest p with
+        // task_start[p] <= tau (matrices without tasks share their successor's start)
+        int lo = 0, hi = a.count;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.task_start[mid] <= tau) lo = mid; else hi = mid;
+        }
+        const int k = a.order[lo];
+        const MatMeta mt = a.meta[k];
+        const uint32_t q = tau - a.task_start[lo];
+
+        int tally = 0;
+        if (a.status[k] == 0) {
+            const RowW *R = a.rows + mt.row_base;
+            StaticRows<UL> sr;
+            if (mt.mode == MODE_FAST) load_static_rows<UL>(R, sr);
+            const uint64_t c = mt.c_first + (uint64_t)q * 64u + (uint64_t)lane;
+            tally = walk_lane<UL>(R, mt.n, mt.m, mt.mode, c, mt.lo, mt.hi, sr);
+        }
+        const int sum = wave_sum(tally);
+
+        if (lane == 0) {
+            if (sum != 0) atomicAdd((unsigned long long *)&a.tally[k], (unsigned long long)(long long)sum);
+            __threadfence();
+            const uint32_t prev = atomicAdd(&a.done[k], 1u);
+            if (prev + 1 == mt.ntasks) {
+                __threadfence();
+                const long long T = __hip_atomic_load((long long *)&a.tally[k], __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                if (a.status[k] != 0) {
+                    a.out[k] = 0xFF;
+                } else {
+                    const uint8_t r = finish_mod3(mt.n, T);
+                    a.out[k] = r;
+                    if (a.hist) atomicAdd((unsigned long long *)&a.hist[3 * mt.n + r], 1ull);
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ serving
+
+template <int UL>
+__global__ void __launch_bounds__(WALK_BLOCK) k_tick(TickArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t total = *a.ntasks;
+    for (;;) {
+        uint32_t tau = 0;
+        if (lane == 0) tau = atomicAdd(a.queue, 1u);
+        tau = __builtin_amdgcn_readfirstlane(tau);
+        if (tau >= total) break;
+        const TickTask tk = a.tasks[tau];
+        const SlotInfo si = a.slots[tk.slot];
+        const RowW *R = a.rows + si.row_base;
+        StaticRows<UL> sr;
+        if (tk.mode == MODE_FAST) load_static_rows<UL>(R, sr);
+        int tally = 0;
+        if (lane < tk.nchunks) {
+            const uint64_t c = tk.c_first + (uint64_t)lane;
+            tally = walk_lane<UL>(R, si.n, tk.m, tk.mode, c, 0, 1ull << si.n, sr);
+        }
+        const int sum = wave_sum(tally);
+        if (lane == 0 && sum != 0)
+            atomicAdd((unsigned long long *)&a.tally[tk.slot], (unsigned long long)(long long)sum);
+    }
+}
+
+__global__ void k_finish(FinishArgs a)
+{
+    const uint32_t nf = *a.nfin;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *a.queue = 0;
+    if (i >= nf) return;
+    const int slot = a.fin_slots[i];
+    const int n = a.slots[slot].n;
+    const long long T = a.tally[slot];
+    a.fin_out[i] = finish_mod3(n, T);
+    a.tally[slot] = 0;
+}
+
+// Pack one matrix into a serving slot.
+__global__ void __launch_bounds__(64) k_slot_pack(const uint8_t *A, int n, RowW *dst)
+{
+    const int r = threadIdx.x;
+    if (r >= n) return;
+    uint64_t mag = 0, sgn = 0;
+    for (int j = 0; j < n; ++j) {
+        const uint8_t v = A[r * n + j];
+        const uint64_t bit = 1ull << (n - 1 - j);
+        if (v != 0) mag |= bit;
+        if (v == 2) sgn |= bit;
+    }
+    store_row(dst + r, mag, sgn);
+}
+
+// ------------------------------------------------------------------ self-check
+
+// Theorem 2.1 on individual 32-bit words, through the same device functions
+// the walk uses.
+__global__ void k_bipedal_ops(const uint32_t *in, int count, uint32_t *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const uint32_t m1 = in[4 * i], s1 = in[4 * i + 1], m2 = in[4 * i + 2], s2 = in[4 * i + 3];
+    uint32_t am = m1, as = s1;
+    bip_add(am, as, m2, s2);
+    uint32_t bm = m1, bs = s1;
+    bip_sub(bm, bs, m2, s2);
+    // the walk's subtraction: add the negated row (sgn xor mag)
+    uint32_t nm = m1, ns = s1;
+    bip_add(nm, ns, m2, s2 ^ m2);
+    out[8 * i + 0] = am;
+    out[8 * i + 1] = as;
+    out[8 * i + 2] = bm;
+    out[8 * i + 3] = bs;
+    out[8 * i + 4] = m1 & m2;   // multiplication
+    out[8 * i + 5] = s1 ^ s2;
+    out[8 * i + 6] = nm;        // subtraction as the walk performs it
+    out[8 * i + 7] = ns;
+}
+
+// ------------------------------------------------------------------ launchers
+
+hipError_t launch_plan(const PlanArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st)
+{
+    if (a.count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_u8, dim3(a.count), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st)
+{
+    if (a.count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pack_planes, dim3(a.count), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk(const WalkArgs &a, int body_log, int grid_blocks, hipStream_t st)
+{
+    switch (body_log) {
+    case 4: hipLaunchKernelGGL(k_walk<4>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    case 5: hipLaunchKernelGGL(k_walk<5>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    case 6: hipLaunchKernelGGL(k_walk<6>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_tick(const TickArgs &a, int body_log, int grid_blocks, hipStream_t st)
+{
+    switch (body_log) {
+    case 4: hipLaunchKernelGGL(k_tick<4>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    case 5: hipLaunchKernelGGL(k_tick<5>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    case 6: hipLaunchKernelGGL(k_tick<6>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const FinishArgs &a, int max_fin, hipStream_t st)
+{
+    const int blocks = max_fin > 0 ? (max_fin + 255) / 256 : 1;
+    hipLaunchKernelGGL(k_finish, dim3(blocks), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_slot_pack(const uint8_t *A, int n, RowW *dst, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_slot_pack, dim3(1), dim3(64), 0, st, A, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_bipedal_ops(const uint32_t *in, int count, uint32_t *out, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bipedal_ops, dim3((count + 63) / 64), dim3(64), 0, st, in, count, out);
+    return hipGetLastError();
+}
+
+}  // namespace perm3

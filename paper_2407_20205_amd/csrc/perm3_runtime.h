@@ -1,0 +1,99 @@
+// Host-side context of libperm3 (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <tuple>
+
+#include "perm3.h"
+#include "perm3_internal.h"
+
+namespace perm3 {
+
+int32_t set_error(int32_t code, const char *fmt, ...);
+void set_error_index(int64_t idx);
+int32_t hip_fail(hipError_t e, const char *what);
+perm_tuning default_tuning();
+bool tuning_valid(const perm_tuning &t);
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf();
+    hipError_t reserve(size_t n);
+};
+
+struct HostBuf {   // pinned host memory
+    void *p = nullptr;
+    size_t cap = 0;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf();
+    hipError_t reserve(size_t n);
+};
+
+// One device launch sequence: plan -> pack -> walk.
+struct Launch {
+    int32_t pack_kind;            // 0: byte matrices, 1: uint64 planes
+    const uint8_t *mats_dev;
+    const int64_t *offs_dev;
+    const uint64_t *planes_dev;
+    const int64_t *row_off_dev;
+    const int32_t *ns_dev;
+    int32_t count;
+    uint8_t *out_dev;
+    uint64_t *hist_dev;
+    int32_t use_range;
+    uint64_t range_lo, range_hi;
+};
+
+using GraphKey = std::tuple<int, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, int, int>;
+
+struct Context {
+    int device = 0;
+    int cus = 0;
+    int clock_khz = 0;
+    char arch[64] = {0};
+    perm_tuning tuning{};
+    hipStream_t stream = nullptr;
+    std::mutex mu;
+
+    DevBuf meta, order, task_start, tally, done, status, counters, rowbuf;
+    DevBuf d_stage, d_out;
+    HostBuf h_stage;
+
+    std::map<GraphKey, hipGraphExec_t> graphs;
+    hipEvent_t ev_walk0 = nullptr, ev_walk1 = nullptr, ev_all0 = nullptr, ev_all1 = nullptr;
+    hipEvent_t ev_done = nullptr, ev_in = nullptr, ev_out = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool last_timing_valid = false;
+    int last_launches = 0;
+    int last_graph = 0;
+
+    ~Context();
+    int waves_total() const;
+    int grid_blocks() const;
+    void drop_graphs();
+    int32_t reserve_work(int32_t count, int64_t rows);
+    int32_t join(hipStream_t st);
+    int32_t mark(hipStream_t st);
+    PlanArgs plan_args(const int32_t *ns_dev, int32_t count, uint8_t *out_dev, uint64_t *hist_dev);
+    WalkArgs walk_args(int32_t count, uint8_t *out_dev, uint64_t *hist_dev);
+    int32_t enqueue(const Launch &L, hipStream_t st, bool timed);
+    int32_t run(const Launch &L, hipStream_t st, bool use_graph);
+    int32_t run_dev(const Launch &L, hipStream_t user);
+    int32_t run_host(const uint8_t *const *As, const int32_t *ns, int32_t count, bool use_range, uint64_t lo,
+                     uint64_t hi, uint8_t *out_host, int64_t *tally_host);
+    int32_t timing(perm_timing *t);
+};
+
+int32_t get_context(Context **out);
+
+}  // namespace perm3

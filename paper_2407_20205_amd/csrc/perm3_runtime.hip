@@ -1,0 +1,680 @@
+// Host runtime of libperm3: the C ABI of include/perm3.h.
+//
+// One context per device holds a stream, growable work buffers, a cache of
+// captured HIP graphs, the tuning table and timing events.  Every compute
+// entry point runs the same three launches on the device:
+//   plan (one workgroup) -> pack (phi, validation) -> persistent walk,
+// so validation, packing, the Gray walk, the reductions and the final mod 3
+// all happen in kernels; host code only checks arguments, moves bytes and
+// launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "perm3.h"
+#include "perm3_internal.h"
+#include "perm3_runtime.h"
+#include "perm3_walk.hpp"
+
+namespace perm3 {
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string tl_error;
+static thread_local int64_t tl_error_index = -1;
+
+int32_t set_error(int32_t code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    tl_error = buf;
+    return code;
+}
+
+void set_error_index(int64_t idx) { tl_error_index = idx; }
+
+int32_t hip_fail(hipError_t e, const char *what)
+{
+    return set_error(PERM_EDEVICE, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+#define HIP_TRY(expr)                                         \
+    do {                                                      \
+        hipError_t _e = (expr);                               \
+        if (_e != hipSuccess) return hip_fail(_e, #expr);     \
+    } while (0)
+
+// ------------------------------------------------------------------ tuning
+
+perm_tuning default_tuning()
+{
+    perm_tuning t;
+    memset(&t, 0, sizeof t);
+    t.waves_per_simd = 8;
+    t.body_log = 5;
+    t.chunk_log_max = 20;
+    t.tasks_per_wave = 8;
+    t.direct_max_n = 16;
+    return t;
+}
+
+bool tuning_valid(const perm_tuning &t)
+{
+    return t.waves_per_simd >= 1 && t.waves_per_simd <= 16 && t.body_log >= 4 && t.body_log <= 6 &&
+           t.chunk_log_max >= 8 && t.chunk_log_max <= 30 && t.tasks_per_wave >= 1 &&
+           t.tasks_per_wave <= 1024 && t.direct_max_n >= t.body_log + 6 && t.direct_max_n <= 63;
+}
+
+// ------------------------------------------------------------------ context
+
+DevBuf::~DevBuf()
+{
+    if (p) (void)hipFree(p);
+}
+
+hipError_t DevBuf::reserve(size_t n)
+{
+    if (n <= cap) return hipSuccess;
+    if (p) {
+        hipError_t e = hipFree(p);
+        p = nullptr;
+        cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    size_t want = std::max<size_t>(n, 256);
+    hipError_t e = hipMalloc(&p, want);
+    if (e == hipSuccess) cap = want;
+    return e;
+}
+
+HostBuf::~HostBuf()
+{
+    if (p) (void)hipHostFree(p);
+}
+
+hipError_t HostBuf::reserve(size_t n)
+{
+    if (n <= cap) return hipSuccess;
+    if (p) {
+        (void)hipHostFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    size_t want = std::max<size_t>(n, 4096);
+    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e == hipSuccess) cap = want;
+    return e;
+}
+
+Context::~Context()
+{
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+    if (ev_walk0) (void)hipEventDestroy(ev_walk0);
+    if (ev_walk1) (void)hipEventDestroy(ev_walk1);
+    if (ev_all0) (void)hipEventDestroy(ev_all0);
+    if (ev_all1) (void)hipEventDestroy(ev_all1);
+    if (ev_done) (void)hipEventDestroy(ev_done);
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+static std::mutex g_ctx_mu;
+static std::map<int, std::unique_ptr<Context>> g_ctx;
+static thread_local bool tl_timing = false;
+
+int32_t get_context(Context **out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> g(g_ctx_mu);
+    auto it = g_ctx.find(dev);
+    if (it != g_ctx.end()) {
+        *out = it->second.get();
+        return PERM_OK;
+    }
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return set_error(PERM_EDEVICE, "device %d is %s; this library is built for gfx950 only", dev,
+                         prop.gcnArchName);
+    std::unique_ptr<Context> c(new Context());
+    c->device = dev;
+    c->cus = prop.multiProcessorCount;
+    c->clock_khz = prop.clockRate;
+    snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+    c->tuning = default_tuning();
+    HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreate(&c->ev_walk0));
+    HIP_TRY(hipEventCreate(&c->ev_walk1));
+    HIP_TRY(hipEventCreate(&c->ev_all0));
+    HIP_TRY(hipEventCreate(&c->ev_all1));
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    *out = c.get();
+    g_ctx[dev] = std::move(c);
+    return PERM_OK;
+}
+
+int Context::waves_total() const { return cus * 4 * tuning.waves_per_simd; }
+int Context::grid_blocks() const { return cus * tuning.waves_per_simd; }
+
+void Context::drop_graphs()
+{
+    for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+}
+
+// Make sure the work buffers hold `count` matrices with `rows` rows in total.
+int32_t Context::reserve_work(int32_t count, int64_t rows)
+{
+    const size_t c = (size_t)std::max(count, 1);
+    void *before[8] = {meta.p, order.p, task_start.p, tally.p, done.p, status.p, counters.p, rowbuf.p};
+    HIP_TRY(meta.reserve(c * sizeof(MatMeta)));
+    HIP_TRY(order.reserve(c * sizeof(int32_t)));
+    HIP_TRY(task_start.reserve((c + 1) * sizeof(uint32_t)));
+    HIP_TRY(tally.reserve(c * sizeof(int64_t)));
+    HIP_TRY(done.reserve(c * sizeof(uint32_t)));
+    HIP_TRY(status.reserve(c));
+    HIP_TRY(counters.reserve(CNT_COUNT * sizeof(uint32_t)));
+    HIP_TRY(rowbuf.reserve((size_t)std::max<int64_t>(rows, 1) * sizeof(RowW)));
+    void *after[8] = {meta.p, order.p, task_start.p, tally.p, done.p, status.p, counters.p, rowbuf.p};
+    if (memcmp(before, after, sizeof before) != 0) drop_graphs();
+    return PERM_OK;
+}
+
+// Order this call after every earlier call of the context (they share buffers).
+int32_t Context::join(hipStream_t st)
+{
+    if (last_stream && last_stream != st) HIP_TRY(hipStreamWaitEvent(st, ev_done, 0));
+    return PERM_OK;
+}
+
+int32_t Context::mark(hipStream_t st)
+{
+    HIP_TRY(hipEventRecord(ev_done, st));
+    last_stream = st;
+    return PERM_OK;
+}
+
+PlanArgs Context::plan_args(const int32_t *ns_dev, int32_t count, uint8_t *out_dev, uint64_t *hist_dev)
+{
+    PlanArgs a;
+    memset(&a, 0, sizeof a);
+    a.ns = ns_dev;
+    a.count = count;
+    a.body_log = tuning.body_log;
+    a.chunk_log_max = tuning.chunk_log_max;
+    a.direct_max_n = tuning.direct_max_n;
+    a.direct_chunk_log_max = 10;
+    a.waves_total = waves_total();
+    a.tasks_per_wave = tuning.tasks_per_wave;
+    a.meta = (MatMeta *)meta.p;
+    a.order = (int32_t *)order.p;
+    a.task_start = (uint32_t *)task_start.p;
+    a.tally = (int64_t *)tally.p;
+    a.done = (uint32_t *)done.p;
+    a.status = (uint8_t *)status.p;
+    a.counters = (uint32_t *)counters.p;
+    a.out = out_dev;
+    a.hist = hist_dev;
+    return a;
+}
+
+WalkArgs Context::walk_args(int32_t count, uint8_t *out_dev, uint64_t *hist_dev)
+{
+    WalkArgs w;
+    w.rows = (const RowW *)rowbuf.p;
+    w.meta = (const MatMeta *)meta.p;
+    w.order = (const int32_t *)order.p;
+    w.task_start = (const uint32_t *)task_start.p;
+    w.count = count;
+    w.tally = (int64_t *)tally.p;
+    w.done = (uint32_t *)done.p;
+    w.status = (const uint8_t *)status.p;
+    w.counters = (uint32_t *)counters.p;
+    w.out = out_dev;
+    w.hist = hist_dev;
+    return w;
+}
+
+// Enqueue plan -> pack -> walk.  pack_kind: 0 bytes, 1 planes.
+int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
+{
+    PlanArgs pa = plan_args(L.ns_dev, L.count, L.out_dev, L.hist_dev);
+    pa.use_range = L.use_range;
+    pa.range_lo = L.range_lo;
+    pa.range_hi = L.range_hi;
+    if (timed) HIP_TRY(hipEventRecord(ev_all0, st));
+    HIP_TRY(launch_plan(pa, st));
+    if (L.pack_kind == 0) {
+        PackU8Args pk;
+        pk.mats = L.mats_dev;
+        pk.offs = L.offs_dev;
+        pk.meta = (const MatMeta *)meta.p;
+        pk.count = L.count;
+        pk.rows = (RowW *)rowbuf.p;
+        pk.status = (uint8_t *)status.p;
+        HIP_TRY(launch_pack_u8(pk, st));
+    } else {
+        PackPlanesArgs pk;
+        pk.planes = L.planes_dev;
+        pk.row_off = L.row_off_dev;
+        pk.meta = (const MatMeta *)meta.p;
+        pk.count = L.count;
+        pk.rows = (RowW *)rowbuf.p;
+        pk.status = (uint8_t *)status.p;
+        HIP_TRY(launch_pack_planes(pk, st));
+    }
+    if (timed) HIP_TRY(hipEventRecord(ev_walk0, st));
+    HIP_TRY(launch_walk(walk_args(L.count, L.out_dev, L.hist_dev), tuning.body_log, grid_blocks(), st));
+    if (timed) {
+        HIP_TRY(hipEventRecord(ev_walk1, st));
+        HIP_TRY(hipEventRecord(ev_all1, st));
+    }
+    last_timing_valid = timed;
+    last_launches = 3;
+    return PERM_OK;
+}
+
+// Run a launch: eagerly when timed, else through a cached HIP graph.
+int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
+{
+    const bool timed = tl_timing;
+    int32_t rc = join(st);
+    if (rc) return rc;
+    last_graph = 0;
+    if (timed || !use_graph) {
+        rc = enqueue(L, st, timed);
+        if (rc) return rc;
+        return mark(st);
+    }
+    GraphKey key{L.pack_kind,
+                 (uintptr_t)(L.pack_kind == 0 ? (const void *)L.mats_dev : (const void *)L.planes_dev),
+                 (uintptr_t)(L.pack_kind == 0 ? (const void *)L.offs_dev : (const void *)L.row_off_dev),
+                 (uintptr_t)L.ns_dev,
+                 (uintptr_t)L.out_dev,
+                 (uintptr_t)L.hist_dev,
+                 (uintptr_t)st,
+                 L.count,
+                 tuning.waves_per_simd * 1000000 + tuning.body_log * 100000 + tuning.chunk_log_max * 1000 +
+                     tuning.tasks_per_wave * 100 + tuning.direct_max_n};
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
+        if (graphs.size() >= 32) drop_graphs();
+        hipGraph_t g = nullptr;
+        HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        rc = enqueue(L, st, false);
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t ex = nullptr;
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+        it = graphs.emplace(key, ex).first;
+    } else {
+        last_graph = 1;
+    }
+    HIP_TRY(hipGraphLaunch(it->second, st));
+    last_timing_valid = false;
+    last_launches = 3;
+    return mark(st);
+}
+
+// A device-input call on the caller's stream, or, for a NULL stream, on the
+// library's stream ordered after earlier and before later work on the legacy
+// default stream (where torch runs unless told otherwise).
+int32_t Context::run_dev(const Launch &L, hipStream_t user)
+{
+    if (user) return run(L, user, true);
+    HIP_TRY(hipEventRecord(ev_in, nullptr));
+    HIP_TRY(hipStreamWaitEvent(stream, ev_in, 0));
+    int32_t rc = run(L, stream, true);
+    if (rc) return rc;
+    HIP_TRY(hipEventRecord(ev_out, stream));
+    HIP_TRY(hipStreamWaitEvent(nullptr, ev_out, 0));
+    return PERM_OK;
+}
+
+// Stage host matrices into device memory (pinned copy) and run them; results
+// to host.  All matrices have been validated by the caller.
+int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t count, bool use_range,
+                          uint64_t lo, uint64_t hi, uint8_t *out_host, int64_t *tally_host)
+{
+    int64_t bytes = 0, rows = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        bytes += (int64_t)ns[k] * ns[k];
+        rows += ns[k];
+    }
+    const size_t offs_bytes = (size_t)count * sizeof(int64_t);
+    const size_t ns_bytes = (size_t)count * sizeof(int32_t);
+    const size_t offs_at = (((size_t)bytes + 15) / 16) * 16;
+    const size_t ns_at = offs_at + offs_bytes;
+    const size_t stage_bytes = ns_at + ns_bytes;
+    HIP_TRY(h_stage.reserve(stage_bytes));
+    HIP_TRY(d_stage.reserve(stage_bytes));
+    HIP_TRY(d_out.reserve((size_t)std::max(count, 1)));
+    int32_t rc = reserve_work(count, rows);
+    if (rc) return rc;
+    uint8_t *h = (uint8_t *)h_stage.p;
+    int64_t *hoffs = (int64_t *)(h + offs_at);
+    int32_t *hns = (int32_t *)(h + ns_at);
+    int64_t o = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        const int64_t sz = (int64_t)ns[k] * ns[k];
+        if (sz) memcpy(h + o, As[k], (size_t)sz);
+        hoffs[k] = o;
+        hns[k] = ns[k];
+        o += sz;
+    }
+    hipStream_t st = stream;
+    rc = join(st);
+    if (rc) return rc;
+    HIP_TRY(hipMemcpyAsync(d_stage.p, h_stage.p, stage_bytes, hipMemcpyHostToDevice, st));
+    uint8_t *d = (uint8_t *)d_stage.p;
+    Launch L;
+    memset(&L, 0, sizeof L);
+    L.pack_kind = 0;
+    L.mats_dev = d;
+    L.offs_dev = (const int64_t *)(d + offs_at);
+    L.ns_dev = (const int32_t *)(d + ns_at);
+    L.count = count;
+    L.out_dev = (uint8_t *)d_out.p;
+    L.hist_dev = nullptr;
+    L.use_range = use_range ? 1 : 0;
+    L.range_lo = lo;
+    L.range_hi = hi;
+    rc = run(L, st, false);
+    if (rc) return rc;
+    if (out_host) HIP_TRY(hipMemcpyAsync(out_host, d_out.p, (size_t)count, hipMemcpyDeviceToHost, st));
+    if (tally_host) HIP_TRY(hipMemcpyAsync(tally_host, tally.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return PERM_OK;
+}
+
+int32_t Context::timing(perm_timing *t)
+{
+    memset(t, 0, sizeof *t);
+    t->launches = last_launches;
+    t->graph_replayed = last_graph;
+    if (!last_timing_valid) return PERM_OK;
+    HIP_TRY(hipEventSynchronize(ev_all1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, ev_walk0, ev_walk1));
+    t->hot_kernel_ms = ms;
+    HIP_TRY(hipEventElapsedTime(&ms, ev_all0, ev_all1));
+    t->total_ms = ms;
+    return PERM_OK;
+}
+
+// ------------------------------------------------------------------ host checks
+
+static int32_t check_matrix(const uint8_t *A, int32_t n, int64_t *bad_at)
+{
+    if (n < 0 || n > PERM_MAX_N) return set_error(PERM_EINVAL, "n = %d is outside [0, %d]", n, PERM_MAX_N);
+    if (n > 0 && !A) return set_error(PERM_EINVAL, "null matrix pointer");
+    const int64_t cells = (int64_t)n * n;
+    for (int64_t i = 0; i < cells; ++i) {
+        if (A[i] > 2) {
+            if (bad_at) *bad_at = i;
+            return set_error(PERM_EDOMAIN, "entry %lld is %u; entries must be 0, 1 or 2", (long long)i,
+                             (unsigned)A[i]);
+        }
+    }
+    return PERM_OK;
+}
+
+}  // namespace perm3
+
+using namespace perm3;
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+int32_t perm_mod3(const uint8_t *A, int32_t n, uint8_t *out)
+{
+    set_error_index(-1);
+    if (!out) return set_error(PERM_EINVAL, "null output pointer");
+    int64_t bad = -1;
+    int32_t rc = check_matrix(A, n, &bad);
+    if (rc) {
+        set_error_index(bad);
+        return rc;
+    }
+    Context *c = nullptr;
+    if ((rc = get_context(&c))) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    const uint8_t *As[1] = {A};
+    int32_t ns[1] = {n};
+    return c->run_host(As, ns, 1, false, 0, 0, out, nullptr);
+}
+
+int32_t perm_mod3_range_tally(const uint8_t *A, int32_t n, uint64_t begin, uint64_t end, int64_t *tally)
+{
+    set_error_index(-1);
+    if (!tally) return set_error(PERM_EINVAL, "null tally pointer");
+    int64_t bad = -1;
+    int32_t rc = check_matrix(A, n, &bad);
+    if (rc) {
+        set_error_index(bad);
+        return rc;
+    }
+    const uint64_t total = 1ull << n;
+    if (begin > end || end > total)
+        return set_error(PERM_EINVAL, "range [%llu, %llu) is not inside [0, 2^%d]", (unsigned long long)begin,
+                         (unsigned long long)end, n);
+    Context *c = nullptr;
+    if ((rc = get_context(&c))) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    const uint8_t *As[1] = {A};
+    int32_t ns[1] = {n};
+    return c->run_host(As, ns, 1, true, begin, end, nullptr, tally);
+}
+
+int32_t perm_mod3_batch(const uint8_t *const *As, const int32_t *ns, int32_t count, uint8_t *out)
+{
+    set_error_index(-1);
+    if (count < 0 || count > PERM_MAX_BATCH) return set_error(PERM_EINVAL, "count = %d out of range", count);
+    if (count == 0) return PERM_OK;
+    if (!As || !ns || !out) return set_error(PERM_EINVAL, "null pointer argument");
+    for (int32_t k = 0; k < count; ++k) {
+        int32_t rc = check_matrix(As[k], ns[k], nullptr);
+        if (rc) {
+            set_error_index(k);
+            return rc;
+        }
+    }
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    return c->run_host(As, ns, count, false, 0, 0, out, nullptr);
+}
+
+int32_t perm_mod3_batch_dev(const uint8_t *mats_dev, const int64_t *offs_dev, const int32_t *ns_dev,
+                            int32_t count, uint8_t *out_dev, uint64_t *hist_dev, void *stream)
+{
+    set_error_index(-1);
+    if (count < 0 || count > PERM_MAX_BATCH) return set_error(PERM_EINVAL, "count = %d out of range", count);
+    if (count == 0) return PERM_OK;
+    if (!mats_dev || !offs_dev || !ns_dev || !out_dev) return set_error(PERM_EINVAL, "null pointer argument");
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    if ((rc = c->reserve_work(count, (int64_t)count * PERM_MAX_N))) return rc;
+    Launch L;
+    memset(&L, 0, sizeof L);
+    L.pack_kind = 0;
+    L.mats_dev = mats_dev;
+    L.offs_dev = offs_dev;
+    L.ns_dev = ns_dev;
+    L.count = count;
+    L.out_dev = out_dev;
+    L.hist_dev = hist_dev;
+    return c->run_dev(L, (hipStream_t)stream);
+}
+
+int32_t perm_mod3_batch_packed(const uint64_t *planes_dev, const int64_t *row_off_dev, const int32_t *ns_dev,
+                               int32_t count, uint8_t *out_dev, uint64_t *hist_dev, void *stream)
+{
+    set_error_index(-1);
+    if (count < 0 || count > PERM_MAX_BATCH) return set_error(PERM_EINVAL, "count = %d out of range", count);
+    if (count == 0) return PERM_OK;
+    if (!planes_dev || !row_off_dev || !ns_dev || !out_dev)
+        return set_error(PERM_EINVAL, "null pointer argument");
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    if ((rc = c->reserve_work(count, (int64_t)count * PERM_MAX_N))) return rc;
+    Launch L;
+    memset(&L, 0, sizeof L);
+    L.pack_kind = 1;
+    L.planes_dev = planes_dev;
+    L.row_off_dev = row_off_dev;
+    L.ns_dev = ns_dev;
+    L.count = count;
+    L.out_dev = out_dev;
+    L.hist_dev = hist_dev;
+    return c->run_dev(L, (hipStream_t)stream);
+}
+
+int32_t perm_mod3_pack(const uint8_t *A, int32_t n, uint64_t *planes)
+{
+    set_error_index(-1);
+    if (!planes && n > 0) return set_error(PERM_EINVAL, "null planes pointer");
+    int64_t bad = -1;
+    int32_t rc = check_matrix(A, n, &bad);
+    if (rc) {
+        set_error_index(bad);
+        return rc;
+    }
+    for (int32_t r = 0; r < n; ++r) {
+        uint64_t mag = 0, sgn = 0;
+        for (int32_t j = 0; j < n; ++j) {
+            const uint8_t v = A[(int64_t)r * n + j];
+            const uint64_t bit = 1ull << (n - 1 - j);
+            if (v != 0) mag |= bit;
+            if (v == 2) sgn |= bit;
+        }
+        planes[2 * r] = mag;
+        planes[2 * r + 1] = sgn;
+    }
+    return PERM_OK;
+}
+
+int32_t perm_tuning_get(perm_tuning *t)
+{
+    if (!t) return set_error(PERM_EINVAL, "null pointer");
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    *t = c->tuning;
+    return PERM_OK;
+}
+
+int32_t perm_tuning_set(const perm_tuning *t)
+{
+    if (!t) return set_error(PERM_EINVAL, "null pointer");
+    if (!tuning_valid(*t)) return set_error(PERM_EINVAL, "tuning out of range");
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    c->tuning = *t;
+    c->drop_graphs();
+    return PERM_OK;
+}
+
+int32_t perm_timing_enable(int32_t on)
+{
+    tl_timing = on != 0;
+    return PERM_OK;
+}
+
+int32_t perm_timing_last(perm_timing *t)
+{
+    if (!t) return set_error(PERM_EINVAL, "null pointer");
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    return c->timing(t);
+}
+
+int32_t perm_device_info_get(perm_device_info *info)
+{
+    if (!info) return set_error(PERM_EINVAL, "null pointer");
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    memset(info, 0, sizeof *info);
+    info->compute_units = c->cus;
+    info->simds_per_cu = 4;
+    info->wave_size = 64;
+    info->max_clock_khz = c->clock_khz;
+    snprintf(info->arch, sizeof info->arch, "%s", c->arch);
+    return PERM_OK;
+}
+
+int32_t perm_bipedal_ops(const uint32_t *in, int32_t count, uint32_t *out)
+{
+    if (count < 0 || count > (1 << 24)) return set_error(PERM_EINVAL, "count out of range");
+    if (count == 0) return PERM_OK;
+    if (!in || !out) return set_error(PERM_EINVAL, "null pointer");
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    DevBuf din, dout;
+    HIP_TRY(din.reserve((size_t)count * 16));
+    HIP_TRY(dout.reserve((size_t)count * 32));
+    HIP_TRY(hipMemcpyAsync(din.p, in, (size_t)count * 16, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(launch_bipedal_ops((const uint32_t *)din.p, count, (uint32_t *)dout.p, c->stream));
+    HIP_TRY(hipMemcpyAsync(out, dout.p, (size_t)count * 32, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return PERM_OK;
+}
+
+const char *perm_strerror(int32_t code)
+{
+    switch (code) {
+    case PERM_OK: return "ok";
+    case PERM_EINVAL: return "invalid argument";
+    case PERM_EDOMAIN: return "matrix entry outside {0,1,2} or packed bit beyond n";
+    case PERM_ENOMEM: return "out of memory";
+    case PERM_EDEVICE: return "HIP device error";
+    case PERM_EAGAIN: return "queue full, try again";
+    case PERM_ESTATE: return "object shut down or busy";
+    default: return "unknown status";
+    }
+}
+
+const char *perm_last_error(void) { return tl_error.c_str(); }
+int64_t perm_last_error_index(void) { return tl_error_index; }
+const char *perm_version(void) { return "perm3 1.0 gfx950"; }
+
+}  // extern "C"

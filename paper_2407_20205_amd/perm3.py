@@ -1,0 +1,301 @@
+"""Thin ctypes binding of libperm3.so (include/perm3.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI.  Loading fails loudly when the library has not been
+built; calls that need the GPU fail with PERM_EDEVICE when there is none.
+torch is used only to hand over device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libperm3.so")
+
+PERM_MAX_N = 63
+PERM_MAX_BATCH = 1 << 22
+PERM_OK = 0
+PERM_EINVAL = -1
+PERM_EDOMAIN = -2
+PERM_ENOMEM = -3
+PERM_EDEVICE = -4
+PERM_EAGAIN = -5
+PERM_ESTATE = -6
+PERM_RESULT_INVALID = 0xFF
+PERM_POLICY_SRPT = 0
+PERM_POLICY_FIFO = 1
+
+
+class PermError(RuntimeError):
+    def __init__(self, code: int, msg: str, index: int = -1):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+        self.index = index
+
+
+class perm_server_cfg(ctypes.Structure):
+    _fields_ = [("max_slots", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
+                ("work_budget", ctypes.c_uint64), ("quantum", ctypes.c_uint64),
+                ("policy", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class perm_done(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("result", ctypes.c_uint8), ("pad", ctypes.c_uint8 * 7),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64)]
+
+
+class perm_server_stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_uint64), ("completed", ctypes.c_uint64),
+                ("ticks", ctypes.c_uint64), ("tick_indices", ctypes.c_uint64),
+                ("busy_ns", ctypes.c_uint64), ("active_slots", ctypes.c_int32),
+                ("queued", ctypes.c_int32)]
+
+
+class perm_tuning(ctypes.Structure):
+    _fields_ = [("waves_per_simd", ctypes.c_int32), ("body_log", ctypes.c_int32),
+                ("chunk_log_max", ctypes.c_int32), ("tasks_per_wave", ctypes.c_int32),
+                ("direct_max_n", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
+class perm_timing(ctypes.Structure):
+    _fields_ = [("hot_kernel_ms", ctypes.c_double), ("total_ms", ctypes.c_double),
+                ("indices", ctypes.c_uint64), ("launches", ctypes.c_int32),
+                ("graph_replayed", ctypes.c_int32)]
+
+
+class perm_device_info(ctypes.Structure):
+    _fields_ = [("compute_units", ctypes.c_int32), ("simds_per_cu", ctypes.c_int32),
+                ("wave_size", ctypes.c_int32), ("max_clock_khz", ctypes.c_int32),
+                ("arch", ctypes.c_char * 64)]
+
+
+# (name, restype, argtypes) for every export of include/perm3.h
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+EXPORTS = [
+    ("perm_mod3", _i32, [_vp, _i32, _vp]),
+    ("perm_mod3_range_tally", _i32, [_vp, _i32, ctypes.c_uint64, ctypes.c_uint64, _vp]),
+    ("perm_mod3_batch", _i32, [_vp, _vp, _i32, _vp]),
+    ("perm_mod3_batch_dev", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    ("perm_mod3_batch_packed", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    ("perm_mod3_pack", _i32, [_vp, _i32, _vp]),
+    ("perm_server_create", _i32, [_vp, _vp]),
+    ("perm_server_submit", _i32, [_vp, _vp, _i32, ctypes.c_uint64]),
+    ("perm_server_poll", _i32, [_vp, _vp, _i32, _vp, ctypes.c_int64]),
+    ("perm_server_stats_get", _i32, [_vp, _vp]),
+    ("perm_server_destroy", _i32, [_vp]),
+    ("perm_tuning_get", _i32, [_vp]),
+    ("perm_tuning_set", _i32, [_vp]),
+    ("perm_autotune", _i32, [_i32, _i32, _vp]),
+    ("perm_timing_enable", _i32, [_i32]),
+    ("perm_timing_last", _i32, [_vp]),
+    ("perm_device_info_get", _i32, [_vp]),
+    ("perm_bipedal_ops", _i32, [_vp, _i32, _vp]),
+    ("perm_strerror", ctypes.c_char_p, [_i32]),
+    ("perm_last_error", ctypes.c_char_p, []),
+    ("perm_last_error_index", ctypes.c_int64, []),
+    ("perm_version", ctypes.c_char_p, []),
+]
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libperm3.so.  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2407_20205_amd.build` (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, res, args in EXPORTS:
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> None:
+    if rc != PERM_OK:
+        L = lib()
+        raise PermError(rc, L.perm_last_error().decode(errors="replace"), L.perm_last_error_index())
+
+
+def _mat(A) -> tuple[np.ndarray, int]:
+    A = np.ascontiguousarray(np.asarray(A, dtype=np.uint8))
+    if A.ndim != 2 or A.shape[0] != A.shape[1]:
+        raise ValueError("square matrix expected")
+    return A, A.shape[0]
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+# ---------------------------------------------------------------- host calls
+
+def perm_mod3(A) -> int:
+    A, n = _mat(A)
+    out = ctypes.c_uint8(0)
+    _check(lib().perm_mod3(_ptr(A) if A.size else None, n, ctypes.addressof(out)))
+    return int(out.value)
+
+
+def perm_mod3_range_tally(A, begin: int, end: int) -> int:
+    A, n = _mat(A)
+    t = ctypes.c_int64(0)
+    _check(lib().perm_mod3_range_tally(_ptr(A) if A.size else None, n, begin, end, ctypes.addressof(t)))
+    return int(t.value)
+
+
+def perm_mod3_batch(mats: Sequence) -> np.ndarray:
+    arrs = [_mat(M)[0] for M in mats]
+    count = len(arrs)
+    ns = np.array([a.shape[0] for a in arrs], dtype=np.int32)
+    ptrs = (ctypes.c_void_p * max(count, 1))(*[a.ctypes.data if a.size else None for a in arrs])
+    out = np.zeros(max(count, 1), dtype=np.uint8)
+    _check(lib().perm_mod3_batch(ptrs, _ptr(ns), count, _ptr(out)))
+    return out[:count]
+
+
+def perm_mod3_pack(A) -> np.ndarray:
+    A, n = _mat(A)
+    planes = np.zeros(max(2 * n, 1), dtype=np.uint64)
+    _check(lib().perm_mod3_pack(_ptr(A) if A.size else None, n, _ptr(planes)))
+    return planes[:2 * n]
+
+
+# ---------------------------------------------------------------- device calls (torch tensors)
+
+def _dptr(t) -> int | None:
+    return None if t is None else int(t.data_ptr())
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return None
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def perm_mod3_batch_dev(mats_dev, offs_dev, ns_dev, out_dev, hist_dev=None, stream=None) -> None:
+    """All tensors on the GPU: uint8 bytes, int64 offsets, int32 n, uint8 out, uint64/int64 hist[64*3]."""
+    count = int(ns_dev.numel())
+    _check(lib().perm_mod3_batch_dev(_dptr(mats_dev), _dptr(offs_dev), _dptr(ns_dev), count,
+                                     _dptr(out_dev), _dptr(hist_dev), _stream(stream)))
+
+
+def perm_mod3_batch_packed(planes_dev, row_off_dev, ns_dev, out_dev, hist_dev=None, stream=None) -> None:
+    count = int(ns_dev.numel())
+    _check(lib().perm_mod3_batch_packed(_dptr(planes_dev), _dptr(row_off_dev), _dptr(ns_dev), count,
+                                        _dptr(out_dev), _dptr(hist_dev), _stream(stream)))
+
+
+# ---------------------------------------------------------------- tuning, timing, device
+
+def tuning_get() -> perm_tuning:
+    t = perm_tuning()
+    _check(lib().perm_tuning_get(ctypes.addressof(t)))
+    return t
+
+
+def tuning_set(t: perm_tuning) -> None:
+    _check(lib().perm_tuning_set(ctypes.addressof(t)))
+
+
+def autotune(n: int, budget_ms: int = 20000) -> perm_tuning:
+    t = perm_tuning()
+    _check(lib().perm_autotune(n, budget_ms, ctypes.addressof(t)))
+    return t
+
+
+def timing_enable(on: bool = True) -> None:
+    _check(lib().perm_timing_enable(1 if on else 0))
+
+
+def timing_last() -> perm_timing:
+    t = perm_timing()
+    _check(lib().perm_timing_last(ctypes.addressof(t)))
+    return t
+
+
+def device_info() -> perm_device_info:
+    d = perm_device_info()
+    _check(lib().perm_device_info_get(ctypes.addressof(d)))
+    return d
+
+
+def bipedal_ops(words: np.ndarray) -> np.ndarray:
+    """words: uint32[count, 4] = (mag1, sgn1, mag2, sgn2) -> uint32[count, 8] (+, -, x, walk's -)."""
+    w = np.ascontiguousarray(words, dtype=np.uint32).reshape(-1, 4)
+    out = np.zeros((max(len(w), 1), 8), dtype=np.uint32)
+    _check(lib().perm_bipedal_ops(_ptr(w), len(w), _ptr(out)))
+    return out[:len(w)]
+
+
+def strerror(code: int) -> str:
+    return lib().perm_strerror(code).decode()
+
+
+def version() -> str:
+    return lib().perm_version().decode()
+
+
+# ---------------------------------------------------------------- serving
+
+class Server:
+    """perm_server_*: continuous-batching request loop (C++ worker thread)."""
+
+    def __init__(self, max_slots: int = 4096, queue_cap: int = 1 << 16, work_budget: int = 0,
+                 quantum: int = 0, policy: int = PERM_POLICY_SRPT):
+        cfg = perm_server_cfg(max_slots, queue_cap, work_budget, quantum, policy, 0)
+        h = ctypes.c_void_p(None)
+        _check(lib().perm_server_create(ctypes.addressof(cfg), ctypes.addressof(h)))
+        self._h = h
+
+    def submit(self, A, tag: int) -> bool:
+        """False when the queue is full (PERM_EAGAIN)."""
+        A, n = _mat(A)
+        rc = lib().perm_server_submit(self._h, _ptr(A) if A.size else None, n, tag)
+        if rc == PERM_EAGAIN:
+            return False
+        _check(rc)
+        return True
+
+    def poll(self, max_items: int = 1024, timeout_us: int = 0) -> list[perm_done]:
+        buf = (perm_done * max_items)()
+        got = ctypes.c_int32(0)
+        _check(lib().perm_server_poll(self._h, buf, max_items, ctypes.addressof(got), timeout_us))
+        return [buf[i] for i in range(got.value)]
+
+    def stats(self) -> perm_server_stats:
+        s = perm_server_stats()
+        _check(lib().perm_server_stats_get(self._h, ctypes.addressof(s)))
+        return s
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(lib().perm_server_destroy(self._h))
+        self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,145 @@
+"""GPU parity for the batched forms (one persistent launch over many matrices)."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import flush_print, oracle_perms, require_gpu, to_dev
+from paper_2407_20205_amd import perm3 as P
+from paper_2407_20205_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    return require_gpu()
+
+
+def dev_inputs(batch):
+    import torch
+    buf, offs = batch.flat()
+    return (to_dev(buf, torch.uint8), to_dev(offs[:-1], torch.int64), to_dev(batch.ns, torch.int32))
+
+
+def packed_inputs(batch):
+    import torch
+    planes = [P.perm_mod3_pack(M) for M in batch.mats]
+    row_off = np.zeros(batch.count, np.int64)
+    row_off[1:] = np.cumsum(batch.ns[:-1].astype(np.int64))
+    flat = np.concatenate(planes) if planes else np.zeros(0, np.uint64)
+    return to_dev(flat.view(np.int64), torch.int64), to_dev(row_off, torch.int64), to_dev(batch.ns, torch.int32)
+
+
+def hist_from(results, ns):
+    h = np.zeros((64, 3), np.int64)
+    for r, n in zip(results, ns):
+        h[int(n), int(r)] += 1
+    return h
+
+
+def test_batch_host_mixed_sizes():
+    b = W.batch_uniform(count=600, n_lo=0, n_hi=22, seed=31)
+    flush_print("oracle on 600 matrices, n in 0..22")
+    want = oracle_perms(b.mats)
+    got = P.perm_mod3_batch(b.mats)
+    assert list(got) == want
+
+
+def test_batch_dev_with_histogram_and_replays():
+    import torch
+    b = W.batch_uniform(count=512, n_lo=12, n_hi=22, seed=32)
+    want = np.array(oracle_perms(b.mats), np.uint8)
+    mats, offs, ns = dev_inputs(b)
+    out = torch.zeros(b.count, dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(64 * 3, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    # the first call captures a graph; later calls replay it, with other device work in between
+    for rep in range(4):
+        out.fill_(0xEE)
+        hist.zero_()
+        P.perm_mod3_batch_dev(mats, offs, ns, out, hist, stream)
+        _ = (torch.arange(1 << 16, device="cuda") * 3).sum().item()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want), rep
+        assert np.array_equal(hist.cpu().numpy().reshape(64, 3), hist_from(want, b.ns)), rep
+
+
+def test_batch_packed_matches_bytes_and_alternative_zero():
+    import torch
+    b = W.batch_uniform(count=256, n_lo=12, n_hi=24, seed=33)
+    want = np.array(oracle_perms(b.mats), np.uint8)
+    planes, row_off, ns = packed_inputs(b)
+    out = torch.zeros(b.count, dtype=torch.uint8, device="cuda")
+    P.perm_mod3_batch_packed(planes, row_off, ns, out, None, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    # (0,1) is also a zero (Definition 2.1): set sgn where mag is clear, inside the n columns
+    p = planes.cpu().numpy().view(np.uint64).copy()
+    g = W.rng(4)
+    r0 = 0
+    for n in b.ns:
+        for r in range(int(n)):
+            mag = int(p[2 * (r0 + r)])
+            noise = int(g.integers(0, 1 << int(n)))
+            p[2 * (r0 + r) + 1] = np.uint64(int(p[2 * (r0 + r) + 1]) | (noise & ~mag))
+        r0 += int(n)
+    out2 = torch.zeros_like(out)
+    P.perm_mod3_batch_packed(to_dev(p.view(np.int64), torch.int64), row_off, ns, out2, None,
+                             torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert np.array_equal(out2.cpu().numpy(), want)
+
+
+def test_batch_invalid_inputs_flagged():
+    import torch
+    b = W.batch_uniform(count=40, n_lo=3, n_hi=20, seed=34)
+    buf, offs = b.flat()
+    buf = buf.copy()
+    bad = [3, 17]
+    for k in bad:
+        buf[offs[k] + 1] = 9
+    ns = b.ns.copy()
+    ns[25] = 70                      # n out of range
+    out = torch.zeros(b.count, dtype=torch.uint8, device="cuda")
+    P.perm_mod3_batch_dev(to_dev(buf, torch.uint8), to_dev(offs[:-1], torch.int64), to_dev(ns, torch.int32), out,
+                          None, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    for k in range(b.count):
+        if k in bad or k == 25:
+            assert got[k] == P.PERM_RESULT_INVALID
+        else:
+            assert got[k] == oracle.perm_mod3(b.mats[k]), k
+    # packed planes with a bit at or above n are rejected
+    planes, row_off, nsd = packed_inputs(b)
+    p = planes.cpu().numpy().view(np.uint64).copy()
+    p[2 * int(row_off[5].item())] |= np.uint64(1) << np.uint64(int(b.ns[5]))
+    out2 = torch.zeros(b.count, dtype=torch.uint8, device="cuda")
+    P.perm_mod3_batch_packed(to_dev(p.view(np.int64), torch.int64), row_off, nsd, out2, None, None)
+    torch.cuda.synchronize()
+    assert out2.cpu().numpy()[5] == P.PERM_RESULT_INVALID
+
+
+def test_monte_carlo_batch_workload_sampled():
+    """8192 matrices, n uniform on 12..28, packed planes: every n <= 20 matrix and a
+    sample of larger ones against the oracle; the histogram against the results."""
+    import torch
+    b = W.batch_uniform()
+    planes, row_off, ns = packed_inputs(b)
+    out = torch.zeros(b.count, dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(64 * 3, dtype=torch.int64, device="cuda")
+    P.perm_mod3_batch_packed(planes, row_off, ns, out, hist, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.array_equal(hist.cpu().numpy().reshape(64, 3), hist_from(got, b.ns))
+    g = W.rng(35)
+    small = [k for k in range(b.count) if b.ns[k] <= 20]
+    big = [int(k) for k in g.choice([k for k in range(b.count) if b.ns[k] > 20], size=24, replace=False)]
+    idx = small + big
+    flush_print(f"oracle on {len(idx)} of the 8192 matrices")
+    want = oracle_perms([b.mats[k] for k in idx])
+    for k, w in zip(idx, want):
+        assert got[k] == w, (k, int(b.ns[k]))
+    # the same matrices alone give the same answers as in the batch
+    for k in big[:6]:
+        assert P.perm_mod3(b.mats[k]) == got[k]
