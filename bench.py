@@ -1,0 +1,335 @@
+"""Benchmark: perm(A) mod 3 by the bipedal Gray-code Ryser sum on one MI355X.
+
+Headline (one step = one whole pass of the method over one 36 x 36 matrix
+already resident in HBM: validate + pack, plan, Gray walk, reduce, mod 3):
+Ryser subset-terms per second, 2^36 - 1 terms per step.  The same JSON line
+carries the walk kernel's roofline position (integer VALU bound), the CPU
+oracle timed on this host, the batched Monte Carlo workload (8192 matrices,
+n = 12..28, one persistent launch) against one launch per matrix, and the
+serving stream (20000 requests, n = 8..40, Poisson arrivals) with p50/p99
+latency against FIFO one-launch-per-request.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only headline|batch|serve]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X vector ALU: 128 32-bit lane-ops per clock per CU (the lane rate behind the
+# published 157.3 TFLOP/s fp32 vector figure: 157.3e12 / 2 flops / 256 CUs / 2.4 GHz),
+# 256 CUs, 2.4 GHz
+PEAK_LANE_OPS = 256 * 128 * 2.4e9
+# lane-ops the method needs per Gray index on gfx950: three 3-input bitwise ops add
+# one row to the 32-bit low word of the subset sum, and one 3-input max per two
+# indices finds candidates (the high word and the sign only for candidates)
+OPS_PER_TERM = 3.5
+# the paper's count for a two-word (n = 33..64 on 32-bit lanes) step: 6 bitwise ops
+# per word for the add/sub plus one compare per word
+PAPER_OPS_PER_TERM_2W = 14
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def pct(x, q):
+    return float(np.percentile(np.asarray(x, dtype=np.float64), q)) if len(x) else float("nan")
+
+
+# ------------------------------------------------------------------ headline
+
+def bench_headline(P, W, torch, steps, warmup):
+    A = W.single_36()
+    n = 36
+    terms = (1 << n) - 1
+    dev = torch.device("cuda", 0)
+    mats = torch.from_numpy(A.reshape(-1).copy()).to(dev)
+    offs = torch.zeros(1, dtype=torch.int64, device=dev)
+    ns = torch.full((1,), n, dtype=torch.int32, device=dev)
+    out = torch.zeros(1, dtype=torch.uint8, device=dev)
+    P.timing_enable(True)
+    for _ in range(warmup):
+        P.perm_mod3_batch_dev(mats, offs, ns, out)
+    torch.cuda.synchronize()
+    hot = []
+    total = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        P.perm_mod3_batch_dev(mats, offs, ns, out)
+        t = P.timing_last()           # waits for this step's events on the library stream
+        hot.append(t.hot_kernel_ms)
+        total.append(t.total_ms)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P.timing_enable(False)
+    result = int(out.item())
+    sec = t1 - t0
+    hot_s = float(np.mean(hot)) * 1e-3
+    achieved = OPS_PER_TERM * terms / hot_s
+    return {
+        "terms_per_s": steps * terms / sec,
+        "ms_per_step": 1e3 * sec / steps,
+        "hot_kernel_ms_mean": float(np.mean(hot)),
+        "hot_kernel_ms_min": float(np.min(hot)),
+        "launches_ms_mean": float(np.mean(total)),
+        "result": result,
+        "roofline": {
+            "bound": "alu",
+            "achieved": achieved / 1e12,
+            "peak": PEAK_LANE_OPS / 1e12,
+            "unit": "T int32 lane-ops/s",
+            "frac": achieved / PEAK_LANE_OPS,
+            "traffic": None,
+            "ops_per_term": OPS_PER_TERM,
+            "terms_per_launch": terms,
+            "kernel": "k_walk<5,1>",
+        },
+        "paper_ops_frac": PAPER_OPS_PER_TERM_2W * terms / hot_s / PEAK_LANE_OPS,
+    }
+
+
+# ------------------------------------------------------------------ batch
+
+def packed_batch(P, W, torch, b):
+    planes = np.concatenate([P.perm_mod3_pack(M) for M in b.mats])
+    row_off = np.zeros(b.count, np.int64)
+    row_off[1:] = np.cumsum(b.ns[:-1].astype(np.int64))
+    dev = torch.device("cuda", 0)
+    return (torch.from_numpy(planes.view(np.int64)).to(dev), torch.from_numpy(row_off).to(dev),
+            torch.from_numpy(b.ns.copy()).to(dev))
+
+
+def bench_batch(P, W, torch, reps):
+    b = W.batch_uniform()
+    terms = int(sum((1 << int(n)) - 1 for n in b.ns))
+    planes, row_off, ns = packed_batch(P, W, torch, b)
+    dev = torch.device("cuda", 0)
+    out = torch.zeros(b.count, dtype=torch.uint8, device=dev)
+    hist = torch.zeros(64 * 3, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+    P.perm_mod3_batch_packed(planes, row_off, ns, out, hist, stream)   # captures the graph
+    torch.cuda.synchronize()
+    hist.zero_()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        P.perm_mod3_batch_packed(planes, row_off, ns, out, hist, stream)
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / reps
+    res = out.cpu().numpy()
+    h = hist.cpu().numpy().reshape(64, 3) // reps
+    per_n = {int(n): [int(x) for x in h[n]] for n in range(12, 29)}
+
+    # baseline: one launch sequence per matrix on the same GPU, no graphs
+    L = P.lib()
+    saved = P.tuning_get()
+    t = P.tuning_get()
+    t.use_graphs = 0
+    P.tuning_set(t)
+    out1 = torch.zeros(b.count, dtype=torch.uint8, device=dev)
+    base_ptr = planes.data_ptr()
+    roff = row_off.cpu().numpy()
+    ns_ptr = ns.data_ptr()
+    zero_off = torch.zeros(1, dtype=torch.int64, device=dev)
+    sh = int(stream.cuda_stream)
+    t0 = time.perf_counter()
+    for k in range(b.count):
+        rc = L.perm_mod3_batch_packed(base_ptr + 16 * int(roff[k]), zero_off.data_ptr(), ns_ptr + 4 * k, 1,
+                                      out1.data_ptr() + k, None, sh)
+        assert rc == 0, P.lib().perm_last_error()
+    torch.cuda.synchronize()
+    sec1 = time.perf_counter() - t0
+    P.tuning_set(saved)
+    same = bool(np.array_equal(out1.cpu().numpy(), res))
+    return {
+        "workload": "8192 matrices, n uniform on 12..28, uniform entries, packed (mag, sgn) uint64 planes",
+        "matrices_per_s": b.count / sec,
+        "terms_per_s": terms / sec,
+        "ms_per_batch": 1e3 * sec,
+        "hist_per_n": per_n,
+        "zero_fraction": float(np.mean(res == 0)),
+        "baseline_one_launch_per_matrix": {"matrices_per_s": b.count / sec1, "ms": 1e3 * sec1,
+                                           "results_identical": same},
+        "speedup_vs_baseline": sec1 / sec,
+    }
+
+
+# ------------------------------------------------------------------ serving
+
+def expected_work(W):
+    support, p = W.serve_n_weights()
+    return float(sum(pi * (2.0 ** int(n)) for n, pi in zip(support, p)))
+
+
+def replay_server(P, tr, policy, quantum):
+    """Open-loop replay: requests are submitted at their arrival times; latency = done - arrival."""
+    count = len(tr.mats)
+    done = {}
+    srv = P.Server(max_slots=4096, queue_cap=1 << 16, work_budget=1 << 44, quantum=quantum, policy=policy)
+    start = time.monotonic_ns()
+    stop = threading.Event()
+
+    def collect():
+        while len(done) < count and not stop.is_set():
+            for d in srv.poll(4096, 2000):
+                done[int(d.tag)] = (int(d.t_done_ns), int(d.result), int(d.t_admit_ns))
+
+    th = threading.Thread(target=collect, daemon=True)
+    th.start()
+    for k in range(count):
+        at = start + int(tr.arrival_s[k] * 1e9)
+        while True:
+            now = time.monotonic_ns()
+            if now >= at:
+                break
+            time.sleep(min(0.0005, (at - now) / 1e9))
+        while not srv.submit(tr.mats[k], k):
+            time.sleep(0.0002)
+    th.join(timeout=600)
+    stop.set()
+    st = srv.stats()
+    srv.close()
+    lat = [(done[k][0] - (start + int(tr.arrival_s[k] * 1e9))) / 1e6 for k in range(count)]
+    end = max(v[0] for v in done.values())
+    return lat, [done[k][1] for k in range(count)], (end - start) / 1e9, st
+
+
+def replay_fifo_baseline(P, tr):
+    """One launch sequence per request, in arrival order, synchronously."""
+    count = len(tr.mats)
+    start = time.monotonic_ns()
+    lat, res = [], []
+    for k in range(count):
+        at = start + int(tr.arrival_s[k] * 1e9)
+        now = time.monotonic_ns()
+        if now < at:
+            time.sleep((at - now) / 1e9)
+        res.append(P.perm_mod3(tr.mats[k]))
+        lat.append((time.monotonic_ns() - at) / 1e6)
+    return lat, res, (time.monotonic_ns() - start) / 1e9
+
+
+def bench_serve(P, W, torch, rate, count, batched_terms_per_s):
+    ew = expected_work(W)
+    if rate is None:
+        rate = 0.7 * batched_terms_per_s / ew
+    tr = W.serve_trace(count=count, rate=rate)
+    terms = float(sum((1 << int(n)) - 1 for n in tr.ns))
+    log(f"serve: {count} requests at {rate:.1f}/s, {terms:.3e} terms")
+    lat, res, span, st = replay_server(P, tr, P.PERM_POLICY_SRPT, 1 << 33)
+    log(f"serve: continuous batching done in {span:.2f} s")
+    blat, bres, bspan = replay_fifo_baseline(P, tr)
+    log(f"serve: FIFO baseline done in {bspan:.2f} s")
+    return {
+        "workload": f"{count} requests, n in 8..40 with P(n) ~ 1.15^-(n-8), Poisson arrivals at {rate:.1f}/s "
+                    "(0.7 x batched capacity / E[2^n]), uniform entries",
+        "rate_per_s": rate,
+        "requests_per_s": count / span,
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(np.mean(lat)),
+        "terms_per_s": terms / span,
+        "ticks": int(st.ticks),
+        "baseline_fifo_one_launch_per_request": {"p50_ms": pct(blat, 50), "p99_ms": pct(blat, 99),
+                                                 "requests_per_s": count / bspan},
+        "results_identical_to_baseline": bool(res == bres),
+    }
+
+
+# ------------------------------------------------------------------ CPU oracle baseline
+
+def bench_cpu(W, seconds=12.0):
+    import oracle
+    threads = oracle.default_threads()
+    A = W.single_36()
+    calib = 1 << 21
+    t0 = time.perf_counter()
+    oracle.range_tally(A, 0, calib * threads, threads=threads)
+    rate = calib * threads / (time.perf_counter() - t0)
+    length = int(min(1 << 36, max(calib * threads, rate * seconds)))
+    a = (1 << 35) - length // 2
+    t0 = time.perf_counter()
+    oracle.range_tally(A, a, a + length, threads=threads)
+    sec = time.perf_counter() - t0
+    return {"value": length / sec, "unit": "subset-terms/s", "cores": threads, "kind": "oracle",
+            "sample": f"Gray indices [{a}, {a + length}) of the 36x36 matrix ({length} of 2^36 terms), "
+                      f"{sec:.1f} s on {threads} threads; full matrix extrapolates to "
+                      f"{(1 << 36) / (length / sec):.0f} s"}
+
+
+# ------------------------------------------------------------------ main
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--only", choices=["headline", "batch", "serve"], default=None)
+    ap.add_argument("--serve-count", type=int, default=20000)
+    ap.add_argument("--serve-rate", type=float, default=None)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one device-to-device copy of this many MiB (a known-size kernel for "
+                         "calibrating the FETCH_SIZE / WRITE_SIZE counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (every box here has one GPU; "
+              "a single matrix would shard its Gray range across GPUs with one int64 sum at the end)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2407_20205_amd import perm3 as P
+    from paper_2407_20205_amd import workloads as W
+    torch.cuda.set_device(0)
+    info = P.device_info()
+    log(f"device {info.arch.decode()} CUs {info.compute_units} clock {info.max_clock_khz} kHz")
+
+    line = {"metric": "Ryser subset-terms/s at n=36 (% int VALU peak); batch matrices/s + p50/p99 latency",
+            "value": None, "unit": "subset-terms/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u32 bitwise / i64 tally", "data": "synthetic (seeded uniform matrices over F_3)",
+            "config": {"workload": "one 36x36 matrix over F_3, iid uniform {0,1,2}, uint8 row-major, "
+                                   "2^36 - 1 Gray-code Ryser terms per step", "n": 36, "global_batch": 1,
+                       "parallelism": "1 GPU, persistent waves over Gray chunks"}}
+
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {nbytes} bytes device to device")
+        del src, dst
+    if args.only in (None, "headline"):
+        h = bench_headline(P, W, torch, args.steps, args.warmup)
+        log(f"headline: {h['terms_per_s']:.4e} terms/s, walk {h['hot_kernel_ms_mean']:.3f} ms, "
+            f"frac {h['roofline']['frac']:.3f}")
+        line["value"] = h["terms_per_s"]
+        line["ms_per_step"] = h["ms_per_step"]
+        line["roofline"] = h["roofline"]
+        line["headline_detail"] = {k: v for k, v in h.items() if k != "roofline"}
+        line["vs_paper_one_core"] = h["terms_per_s"] / ((1 << 36) / 101.9)
+    if args.only in (None, "batch"):
+        bt = bench_batch(P, W, torch, reps=max(3, args.steps // 4))
+        log(f"batch: {bt['matrices_per_s']:.1f} matrices/s ({bt['speedup_vs_baseline']:.1f}x one-launch)")
+        line["batch"] = bt
+    if args.only in (None, "serve"):
+        cap = line.get("batch", {}).get("terms_per_s") or 8e12
+        line["serve"] = bench_serve(P, W, torch, args.serve_rate, args.serve_count, cap)
+    if args.only is None and not args.no_cpu:
+        line["cpu_baseline"] = bench_cpu(W)
+        log(f"cpu oracle: {line['cpu_baseline']['value']:.3e} terms/s on {line['cpu_baseline']['cores']} threads")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

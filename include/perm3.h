@@ -198,7 +198,9 @@ typedef struct {
     int32_t chunk_log_max;    /* largest per-lane chunk, log2 Gray indices (8..30)      */
     int32_t tasks_per_wave;   /* target tasks per persistent wave for large matrices    */
     int32_t direct_max_n;     /* n at or below which every step is tested exactly      */
-    int32_t reserved[3];
+    int32_t use_graphs;       /* 1: capture device-input calls into cached HIP graphs   */
+    int32_t states_per_lane;  /* chunks a lane walks side by side: 1, 2 or 4            */
+    int32_t reserved[1];
 } perm_tuning;
 
 int32_t perm_tuning_get(perm_tuning *t);

@@ -1,8 +1,9 @@
 // perm_autotune: pick the walk's launch shape by timing it on the device.
 //
-// Candidates vary the persistent waves per SIMD, the unrolled block length
-// (2^body_log Gray steps), the task granularity and, for small n, the size
-// at or below which every index is tested exactly.  Each candidate walks the
+// Candidates vary the persistent waves per SIMD, the chunks each lane walks
+// side by side, the unrolled block length (2^body_log Gray steps), the task
+// granularity and, for small n, the size at or below which every index is
+// tested exactly.  Each candidate walks the
 // same pseudo-random matrix of the requested n over a Gray index range long
 // enough to fill the machine; the one with the most indices per second wins
 // and becomes the context's tuning.
@@ -58,8 +59,10 @@ extern "C" int32_t perm_autotune(int32_t n, int32_t budget_ms, perm_tuning *best
     const int tpws[] = {8, 4, 16};
     const int dmx[] = {16, 20, 14, 24};
     const int ndm = n <= 24 ? 4 : 1;
+    const int sts[] = {2, 1, 4};
 
     for (int di = 0; di < ndm; ++di)
+      for (int st : sts)
         for (int bl : bls)
             for (int tpw : tpws)
                 for (int wp : wps) {
@@ -71,6 +74,7 @@ extern "C" int32_t perm_autotune(int32_t n, int32_t budget_ms, perm_tuning *best
                     t.body_log = bl;
                     t.tasks_per_wave = tpw;
                     t.direct_max_n = dmx[di] < bl + 6 ? bl + 6 : dmx[di];
+                    t.states_per_lane = st;
                     if (!tuning_valid(t)) continue;
                     c->tuning = t;
                     const uint8_t *As[1] = {A.data()};

@@ -19,7 +19,7 @@ struct MatMeta {
     int32_t n;
     int32_t m;          // log2 of the per-lane chunk length
     int32_t mode;       // WalkMode
-    uint32_t ntasks;    // 64 chunks per task
+    uint32_t ntasks;    // 64 * S chunks per task
     int64_t row_base;   // first RowW of this matrix
     uint64_t lo, hi;    // Gray index range [lo, hi)
     uint64_t c_first;   // first chunk index (lo >> m)
@@ -34,6 +34,7 @@ struct PlanArgs {
     int32_t use_range;            // 1: matrix 0 walks [range_lo, range_hi) only (count == 1)
     uint64_t range_lo, range_hi;
     int32_t body_log, chunk_log_max, direct_max_n, direct_chunk_log_max;
+    int32_t states_log;           // log2 of the chunks a lane carries side by side
     int32_t waves_total, tasks_per_wave;
     MatMeta *meta;
     int32_t *order;               // [count] matrix index by decreasing n
@@ -114,7 +115,7 @@ struct FinishArgs {
 hipError_t launch_plan(const PlanArgs &a, hipStream_t st);
 hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st);
 hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st);
-hipError_t launch_walk(const WalkArgs &a, int body_log, int grid_blocks, hipStream_t st);
+hipError_t launch_walk(const WalkArgs &a, int body_log, int states, int grid_blocks, hipStream_t st);
 hipError_t launch_tick(const TickArgs &a, int body_log, int grid_blocks, hipStream_t st);
 hipError_t launch_finish(const FinishArgs &a, int max_fin, hipStream_t st);
 hipError_t launch_slot_pack(const uint8_t *A, int n, RowW *dst, hipStream_t st);

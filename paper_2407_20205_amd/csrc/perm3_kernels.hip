@@ -22,6 +22,31 @@ namespace perm3 {
 
 // ------------------------------------------------------------------ helpers
 
+// Read-only data seen through the constant address space: wave-uniform loads
+// from it become scalar loads into SGPRs.
+#define PERM3_CONST __attribute__((address_space(4)))
+template <typename T>
+using cptr = const PERM3_CONST T *;
+
+template <typename T>
+__device__ __forceinline__ cptr<T> to_const(const T *p)
+{
+    return reinterpret_cast<cptr<T>>(reinterpret_cast<uintptr_t>(p));
+}
+
+// p[i] copied out word by word (wave-uniform i: scalar loads).
+template <typename T>
+__device__ __forceinline__ T load_const(const T *p, int64_t i)
+{
+    static_assert(sizeof(T) % 4 == 0, "word-sized records");
+    const cptr<uint32_t> w = reinterpret_cast<cptr<uint32_t>>(reinterpret_cast<uintptr_t>(p + i));
+    T v;
+    uint32_t *d = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (size_t k = 0; k < sizeof(T) / 4; ++k) d[k] = w[k];
+    return v;
+}
+
 __device__ __forceinline__ Masks masks_for(int n)
 {
     const uint64_t full = (n >= 64) ? ~0ull : ((1ull << n) - 1ull);
@@ -54,7 +79,7 @@ __device__ __forceinline__ uint8_t finish_mod3(int n, long long T)
 }
 
 template <int UL>
-__device__ __forceinline__ void load_static_rows(const RowW *__restrict__ R, StaticRows<UL> &sr)
+__device__ __forceinline__ void load_static_rows(cptr<RowW> R, StaticRows<UL> &sr)
 {
 #pragma unroll
     for (int t = 0; t < UL; ++t) {
@@ -66,7 +91,7 @@ __device__ __forceinline__ void load_static_rows(const RowW *__restrict__ R, Sta
 
 // Walk one lane's chunk c (chunk length 2^m) clipped to [lo, hi).
 template <int UL>
-__device__ __forceinline__ int walk_lane(const RowW *__restrict__ R, int n, int m, int mode, uint64_t c,
+__device__ __forceinline__ int walk_lane(cptr<RowW> R, int n, int m, int mode, uint64_t c,
                                          uint64_t lo, uint64_t hi, const StaticRows<UL> &sr)
 {
     const Masks mk = masks_for(n);
@@ -75,8 +100,29 @@ __device__ __forceinline__ int walk_lane(const RowW *__restrict__ R, int n, int 
     const uint64_t a = a0 > lo ? a0 : lo;
     const uint64_t e = e0 < hi ? e0 : hi;
     if (a >= e) return 0;
-    if (mode == MODE_FAST && a == a0 && e == e0) return walk_chunk_fast<UL>(R, n, m, c, mk, sr);
+    if (mode == MODE_FAST && a == a0 && e == e0) return walk_chunks_fast<UL, 1>(R, n, m, c, mk, sr);
     return n > 32 ? walk_range_direct<true>(R, n, a, e, mk) : walk_range_direct<false>(R, n, a, e, mk);
+}
+
+// Walk a lane's S chunks c + 64 s, s = 0 .. S-1, clipped to [lo, hi): side by
+// side when all are whole fast-mode chunks, else one after another.
+template <int UL, int S>
+__device__ __forceinline__ int walk_lane_states(cptr<RowW> R, int n, int m, int mode, uint64_t c,
+                                                uint64_t lo, uint64_t hi, const StaticRows<UL> &sr)
+{
+    if (S > 1 && mode == MODE_FAST) {
+        bool whole = true;
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+            const uint64_t a0 = (c + 64u * (uint64_t)q) << m;
+            whole &= a0 >= lo && a0 + (1ull << m) <= hi;
+        }
+        if (whole) return walk_chunks_fast<UL, S>(R, n, m, c, masks_for(n), sr);
+    }
+    int tally = 0;
+#pragma unroll
+    for (int q = 0; q < S; ++q) tally += walk_lane<UL>(R, n, m, mode, c + 64u * (uint64_t)q, lo, hi, sr);
+    return tally;
 }
 
 // ------------------------------------------------------------------ plan
@@ -157,7 +203,7 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
     int target_m = 0;
     if (per_task >= 128.0) {
         const uint64_t pt = (uint64_t)per_task;
-        target_m = (63 - __builtin_clzll(pt)) - 6;
+        target_m = (63 - __builtin_clzll(pt)) - 6 - a.states_log;
     }
 
     for (int k = tid; k < a.count; k += 1024) {
@@ -186,10 +232,11 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
             range_of(a, n, lo, hi);
             mt.lo = lo;
             mt.hi = hi;
-            const bool fast_ok = n >= a.body_log + 7 && n > a.direct_max_n;
+            const int slog = a.states_log;
+            const bool fast_ok = n >= a.body_log + 7 + slog && n > a.direct_max_n;
             int m;
             if (fast_ok) {
-                const int mmax = a.chunk_log_max < n - 6 ? a.chunk_log_max : n - 6;
+                const int mmax = a.chunk_log_max < n - 6 - slog ? a.chunk_log_max : n - 6 - slog;
                 m = target_m;
                 if (m > mmax) m = mmax;
                 if (m < a.body_log + 1) m = a.body_log + 1;
@@ -205,7 +252,8 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
                 const uint64_t c0 = lo >> m;
                 const uint64_t c1 = (hi - 1) >> m;
                 mt.c_first = c0;
-                mt.ntasks = (uint32_t)((c1 - c0 + 1 + 63) >> 6);
+                const uint64_t per_task = 64ull << a.states_log;
+                mt.ntasks = (uint32_t)((c1 - c0 + per_task) / per_task);
             } else {
                 mt.mode = MODE_NONE;
                 a.out[k] = finish_mod3(n, 0);
@@ -305,7 +353,7 @@ __global__ void __launch_bounds__(64) k_pack_planes(PackPlanesArgs a)
 
 // ------------------------------------------------------------------ walk
 
-template <int UL>
+template <int UL, int S>
 __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -318,22 +366,23 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
 
         // position p in the order whose tasks contain tau: the largest p with
         // task_start[p] <= tau (matrices without tasks share their successor's start)
+        const cptr<uint32_t> task_start = to_const(a.task_start);
         int lo = 0, hi = a.count;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (a.task_start[mid] <= tau) lo = mid; else hi = mid;
+            if (task_start[mid] <= tau) lo = mid; else hi = mid;
         }
-        const int k = a.order[lo];
-        const MatMeta mt = a.meta[k];
-        const uint32_t q = tau - a.task_start[lo];
+        const int k = to_const(a.order)[lo];
+        const MatMeta mt = load_const(a.meta, k);
+        const uint32_t q = tau - task_start[lo];
 
         int tally = 0;
-        if (a.status[k] == 0) {
-            const RowW *R = a.rows + mt.row_base;
+        if (to_const(a.status)[k] == 0) {
+            const cptr<RowW> R = to_const(a.rows) + mt.row_base;
             StaticRows<UL> sr;
             if (mt.mode == MODE_FAST) load_static_rows<UL>(R, sr);
-            const uint64_t c = mt.c_first + (uint64_t)q * 64u + (uint64_t)lane;
-            tally = walk_lane<UL>(R, mt.n, mt.m, mt.mode, c, mt.lo, mt.hi, sr);
+            const uint64_t c = mt.c_first + (uint64_t)q * (64u * S) + (uint64_t)lane;
+            tally = walk_lane_states<UL, S>(R, mt.n, mt.m, mt.mode, c, mt.lo, mt.hi, sr);
         }
         const int sum = wave_sum(tally);
 
@@ -369,9 +418,9 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_tick(TickArgs a)
         if (lane == 0) tau = atomicAdd(a.queue, 1u);
         tau = __builtin_amdgcn_readfirstlane(tau);
         if (tau >= total) break;
-        const TickTask tk = a.tasks[tau];
-        const SlotInfo si = a.slots[tk.slot];
-        const RowW *R = a.rows + si.row_base;
+        const TickTask tk = load_const(a.tasks, tau);
+        const SlotInfo si = load_const(a.slots, tk.slot);
+        const cptr<RowW> R = to_const(a.rows) + si.row_base;
         StaticRows<UL> sr;
         if (tk.mode == MODE_FAST) load_static_rows<UL>(R, sr);
         int tally = 0;
@@ -461,12 +510,23 @@ hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_walk(const WalkArgs &a, int body_log, int grid_blocks, hipStream_t st)
+template <int UL>
+static void launch_walk_s(const WalkArgs &a, int states, int grid_blocks, hipStream_t st)
 {
+    switch (states) {
+    case 1: hipLaunchKernelGGL((k_walk<UL, 1>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_walk<UL, 2>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    default: hipLaunchKernelGGL((k_walk<UL, 4>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    }
+}
+
+hipError_t launch_walk(const WalkArgs &a, int body_log, int states, int grid_blocks, hipStream_t st)
+{
+    if (states != 1 && states != 2 && states != 4) return hipErrorInvalidValue;
     switch (body_log) {
-    case 4: hipLaunchKernelGGL(k_walk<4>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
-    case 5: hipLaunchKernelGGL(k_walk<5>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
-    case 6: hipLaunchKernelGGL(k_walk<6>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    case 4: launch_walk_s<4>(a, states, grid_blocks, st); break;
+    case 5: launch_walk_s<5>(a, states, grid_blocks, st); break;
+    case 6: launch_walk_s<6>(a, states, grid_blocks, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

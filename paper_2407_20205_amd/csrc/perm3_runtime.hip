@@ -65,8 +65,10 @@ perm_tuning default_tuning()
     t.waves_per_simd = 8;
     t.body_log = 5;
     t.chunk_log_max = 20;
-    t.tasks_per_wave = 8;
+    t.tasks_per_wave = 16;
     t.direct_max_n = 16;
+    t.use_graphs = 1;
+    t.states_per_lane = 1;
     return t;
 }
 
@@ -74,7 +76,9 @@ bool tuning_valid(const perm_tuning &t)
 {
     return t.waves_per_simd >= 1 && t.waves_per_simd <= 16 && t.body_log >= 4 && t.body_log <= 6 &&
            t.chunk_log_max >= 8 && t.chunk_log_max <= 30 && t.tasks_per_wave >= 1 &&
-           t.tasks_per_wave <= 1024 && t.direct_max_n >= t.body_log + 6 && t.direct_max_n <= 63;
+           t.tasks_per_wave <= 1024 && t.direct_max_n >= t.body_log + 6 && t.direct_max_n <= 63 &&
+           (t.use_graphs == 0 || t.use_graphs == 1) &&
+           (t.states_per_lane == 1 || t.states_per_lane == 2 || t.states_per_lane == 4);
 }
 
 // ------------------------------------------------------------------ context
@@ -223,6 +227,7 @@ PlanArgs Context::plan_args(const int32_t *ns_dev, int32_t count, uint8_t *out_d
     a.chunk_log_max = tuning.chunk_log_max;
     a.direct_max_n = tuning.direct_max_n;
     a.direct_chunk_log_max = 10;
+    a.states_log = tuning.states_per_lane == 4 ? 2 : (tuning.states_per_lane == 2 ? 1 : 0);
     a.waves_total = waves_total();
     a.tasks_per_wave = tuning.tasks_per_wave;
     a.meta = (MatMeta *)meta.p;
@@ -283,7 +288,8 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
         HIP_TRY(launch_pack_planes(pk, st));
     }
     if (timed) HIP_TRY(hipEventRecord(ev_walk0, st));
-    HIP_TRY(launch_walk(walk_args(L.count, L.out_dev, L.hist_dev), tuning.body_log, grid_blocks(), st));
+    HIP_TRY(launch_walk(walk_args(L.count, L.out_dev, L.hist_dev), tuning.body_log, tuning.states_per_lane,
+                        grid_blocks(), st));
     if (timed) {
         HIP_TRY(hipEventRecord(ev_walk1, st));
         HIP_TRY(hipEventRecord(ev_all1, st));
@@ -300,7 +306,7 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
     int32_t rc = join(st);
     if (rc) return rc;
     last_graph = 0;
-    if (timed || !use_graph) {
+    if (timed || !use_graph || !tuning.use_graphs) {
         rc = enqueue(L, st, timed);
         if (rc) return rc;
         return mark(st);
@@ -314,7 +320,7 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
                  (uintptr_t)st,
                  L.count,
                  tuning.waves_per_simd * 1000000 + tuning.body_log * 100000 + tuning.chunk_log_max * 1000 +
-                     tuning.tasks_per_wave * 100 + tuning.direct_max_n};
+                     tuning.tasks_per_wave * 100 + tuning.direct_max_n + tuning.states_per_lane * 10000000};
     auto it = graphs.find(key);
     if (it == graphs.end()) {
         if (graphs.size() >= 32) drop_graphs();

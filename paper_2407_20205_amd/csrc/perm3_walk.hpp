@@ -68,8 +68,8 @@ struct Masks {
 // zero unless every column sum is non-zero.  The high words are not carried
 // by the fast walk; when the low words pass, they are formed here from
 // scratch by summing the rows of g(i) (rare: a (2/3)^32 event per index).
-PERM3_FN int exact_term(const RowW *__restrict__ R, int n, uint64_t i, uint32_t ml, uint32_t sl,
-                        Masks mk)
+template <typename RP>
+PERM3_FN int exact_term(RP R, int n, uint64_t i, uint32_t ml, uint32_t sl, Masks mk)
 {
     if (ml != mk.lo) return 0;
     uint32_t mh = 0, sh = 0;
@@ -85,7 +85,8 @@ PERM3_FN int exact_term(const RowW *__restrict__ R, int n, uint64_t i, uint32_t 
 
 // Low words of the subset sum of g(i0): jump straight to a Gray state
 // (Section 3.1).  O(n) word operations per lane.
-PERM3_FN void seed_lo(const RowW *__restrict__ R, int n, uint64_t i0, uint32_t &ml, uint32_t &sl)
+template <typename RP>
+PERM3_FN void seed_lo(RP R, int n, uint64_t i0, uint32_t &ml, uint32_t &sl)
 {
     const uint64_t g = i0 ^ (i0 >> 1);
     ml = 0;
@@ -96,18 +97,37 @@ PERM3_FN void seed_lo(const RowW *__restrict__ R, int n, uint64_t i0, uint32_t &
     }
 }
 
-// Exact re-walk of one block of the fast walk, for the lanes whose block
-// contained a candidate.  Starts from the state at chunk offset b*2^UL and
-// visits offsets b*2^UL + 1 .. jend with an exact test of every index.
+// Static rows of the unrolled block: t = 0 .. UL-1, wave-uniform.
 template <int UL>
-PERM3_FN int replay_block(const RowW *__restrict__ R, int n, uint64_t i0, uint32_t b, uint32_t nb,
-                          uint32_t ml, uint32_t sl, Masks mk)
+struct StaticRows {
+    uint32_t m[UL], s[UL], sn[UL];
+};
+
+// A wave-uniform word moved into a vector register.  bitop3 with a scalar
+// operand issues more slowly than with three vector operands on gfx950, so
+// the rows the block adds are kept in VGPRs.
+#ifndef PERM3_TO_VGPR
+#define PERM3_TO_VGPR(x) perm3::to_vgpr(x)
+PERM3_FN uint32_t to_vgpr(uint32_t x)
 {
+    uint32_t v;
+    asm volatile("v_mov_b32 %0, %1" : "=v"(v) : "s"(x));
+    return v;
+}
+#endif
+
+// Exact re-walk of Gray indices ia+1 .. ib (ia itself already counted) for
+// the lanes whose block held a candidate: the low words are re-seeded at ia
+// from the Gray state and stepped; the high words are formed only where the
+// low words pass.  Lean on registers, so it can sit inside the walk loop.
+template <typename RP>
+PERM3_FN int rewalk_exact(RP R, int n, uint64_t ia, uint64_t ib, Masks mk)
+{
+    uint32_t ml, sl;
+    seed_lo(R, n, ia, ml, sl);
     int tally = 0;
-    const uint32_t jend = (b + 1 < nb) ? ((b + 1) << UL) : (((b + 1) << UL) - 1);
-    for (uint32_t j = (b << UL) + 1; j <= jend; ++j) {
-        const uint64_t i = i0 + j;
-        const int t = __builtin_ctz(j);
+    for (uint64_t i = ia + 1; i <= ib; ++i) {
+        const int t = __builtin_ctzll(i);
         const bool leave = (i >> (t + 1)) & 1u;
         bip_add(ml, sl, R[t].m_lo, leave ? R[t].sn_lo : R[t].s_lo);
         tally += exact_term(R, n, i, ml, sl, mk);
@@ -115,71 +135,114 @@ PERM3_FN int replay_block(const RowW *__restrict__ R, int n, uint64_t i0, uint32
     return tally;
 }
 
-// Static rows of the unrolled block: t = 0 .. UL-1, wave-uniform.
-template <int UL>
-struct StaticRows {
-    uint32_t m[UL], s[UL], sn[UL];
-};
-
-// Fast walk of one whole aligned chunk [c*2^m, (c+1)*2^m), m > UL.
+// Fast walk of S whole aligned chunks c + 64 s (s = 0 .. S-1) of length
+// 2^m, m > UL, carried side by side in one lane.
 //
-// The chunk is cut into nb = 2^(m-UL) blocks of 2^UL indices.  Inside a
+// Each chunk is cut into nb = 2^(m-UL) blocks of 2^UL indices.  Inside a
 // block the flipped row t = ctz(offset) and its direction are compile-time
 // constants except for the middle step (t = UL-1, direction = parity of the
-// block number), so the rows sit in scalar registers and each index costs
-// the three bitop3 of the addition.  The step into the next block flips a
-// row t >= UL chosen at run time (t = m-1 once per chunk, with a direction
-// given by the chunk's parity).
+// block number), so each index costs the three bitop3 of the addition, with
+// the rows held in vector registers.  The step into the next block flips a
+// row t >= UL chosen at run time; its row and direction are wave-uniform.
+// The one step of a chunk whose direction differs between lanes (t = m-1,
+// entering the second half; the row leaves the subset when the chunk index
+// is odd) sits between the two halves' loops.  The last block of each half
+// adds a zero row instead of a boundary step, which keeps the block body
+// free of branches.  Chunks 64 apart have the same parity, so the S states
+// take exactly the same row operations: S independent dependency chains.
 //
 // Candidates are found a block at a time: with bits >= n of every row zero,
 // each low mag word is <= mk.lo, so the block's maximum equals mk.lo exactly
-// when some index in it has all its low columns non-zero.  Only then is the
-// block re-walked exactly (replay_block).
-template <int UL>
-PERM3_FN int walk_chunk_fast(const RowW *__restrict__ R, int n, int m, uint64_t c, Masks mk,
-                             const StaticRows<UL> &sr)
+// when some index in it has all its low columns non-zero (one 3-input max
+// per two states, or per two steps when S = 1).  Only then is the block
+// walked again exactly (rewalk_exact from the block's first index).
+template <int UL, int S, typename RP>
+PERM3_FN int walk_chunks_fast(RP R, int n, int m, uint64_t c, Masks mk, const StaticRows<UL> &sr)
 {
-    const uint64_t i0 = c << m;
-    uint32_t ml, sl;
-    seed_lo(R, n, i0, ml, sl);
-    int tally = exact_term(R, n, i0, ml, sl, mk);
-    const uint32_t nb = 1u << (m - UL);
-    const bool codd = (c & 1u) != 0;
-    for (uint32_t b = 0; b < nb; ++b) {
-        const uint32_t m0 = ml, s0 = sl;
-        uint32_t acc = 0;
+    static_assert(S == 1 || S == 2 || S == 4, "1, 2 or 4 states per lane");
+    constexpr uint32_t U = 1u << UL;
+    uint32_t ml[S], sl[S];
+    int tally = 0;
 #pragma unroll
-        for (int k = 1; k < (1 << UL); ++k) {
-            const int t = __builtin_ctz(k);
-            uint32_t rs;
-            if (t < UL - 1)
-                rs = ((k >> (t + 1)) & 1) ? sr.sn[t] : sr.s[t];
-            else
-                rs = (b & 1u) ? sr.sn[t] : sr.s[t];
-            bip_add(ml, sl, sr.m[t], rs);
-            acc = k == 1 ? ml : (acc > ml ? acc : ml);
-        }
-        if (b + 1 < nb) {
+    for (int q = 0; q < S; ++q) {
+        const uint64_t i0 = (c + 64u * (uint64_t)q) << m;
+        seed_lo(R, n, i0, ml[q], sl[q]);
+        tally += exact_term(R, n, i0, ml[q], sl[q], mk);
+    }
+    // static rows as vector registers
+    uint32_t vm[UL], vs[UL], vsn[UL];
+#pragma unroll
+    for (int t = 0; t < UL; ++t) {
+        vm[t] = PERM3_TO_VGPR(sr.m[t]);
+        vs[t] = PERM3_TO_VGPR(sr.s[t]);
+        vsn[t] = PERM3_TO_VGPR(sr.sn[t]);
+    }
+    const uint32_t half = 1u << (m - UL - 1);
+    for (uint32_t h = 0; h < 2; ++h) {
+        const uint32_t bend = (h + 1) * half;
+        for (uint32_t b = h * half; b < bend; ++b) {
+            // boundary step into block b+1 when it lies in this half (t < m-1)
             const uint32_t jb = b + 1;
-            const int t = UL + __builtin_ctz(jb);
-            const uint32_t bm = R[t].m_lo, bs = R[t].s_lo, bsn = R[t].sn_lo;
-            bool leave;
-            if (t + 1 < m)
-                leave = (jb >> (t + 1 - UL)) & 1u;
-            else
-                leave = codd;
-            bip_add(ml, sl, bm, leave ? bsn : bs);
-            acc = acc > ml ? acc : ml;
+            const bool inner = jb < bend;
+            const int tb = UL + __builtin_ctz(jb);      // <= m < n: in range even when unused
+            const bool leave = (jb >> (tb + 1 - UL)) & 1u;
+            const uint32_t bm = PERM3_TO_VGPR(inner ? R[tb].m_lo : 0u);
+            const uint32_t bs = PERM3_TO_VGPR(inner ? (leave ? R[tb].sn_lo : R[tb].s_lo) : 0u);
+            uint32_t acc = 0;
+#pragma unroll
+            for (int k = 1; k <= (int)U; ++k) {
+                uint32_t rm, rs;
+                if (k < (int)U) {
+                    const int t = __builtin_ctz(k);
+                    rm = vm[t];
+                    if (t < UL - 1)
+                        rs = ((k >> (t + 1)) & 1) ? vsn[t] : vs[t];
+                    else
+                        rs = (b & 1u) ? vsn[t] : vs[t];
+                } else {
+                    rm = bm;
+                    rs = bs;
+                }
+#pragma unroll
+                for (int q = 0; q < S; ++q) bip_add(ml[q], sl[q], rm, rs);
+                if (S == 1) {
+                    acc = k == 1 ? ml[0] : (acc > ml[0] ? acc : ml[0]);
+                } else {
+                    // max(max(acc, a), b): one v_max3_u32 per pair of states
+#pragma unroll
+                    for (int q = 0; q < S; q += 2) {
+                        const uint32_t x = acc > ml[q] ? acc : ml[q];
+                        acc = x > ml[q + 1] ? x : ml[q + 1];
+                    }
+                }
+            }
+            if (acc == mk.lo) {
+                const uint32_t last = b * U + U - (inner ? 0u : 1u);
+#pragma unroll
+                for (int q = 0; q < S; ++q) {
+                    const uint64_t i0 = (c + 64u * (uint64_t)q) << m;
+                    tally += rewalk_exact(R, n, i0 + b * U, i0 + last, mk);
+                }
+            }
         }
-        if (acc == mk.lo) tally += replay_block<UL>(R, n, i0, b, nb, m0, s0, mk);
+        if (h == 0) {
+            // offset L/2 flips row m-1
+            const bool odd = (c & 1u) != 0;
+            const uint32_t rm = R[m - 1].m_lo, rs = odd ? R[m - 1].sn_lo : R[m - 1].s_lo;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                bip_add(ml[q], sl[q], rm, rs);
+                tally += exact_term(R, n, ((c + 64u * (uint64_t)q) << m) + ((uint64_t)half << UL), ml[q], sl[q], mk);
+            }
+        }
     }
     return tally;
 }
 
 // Exact walk of an arbitrary range [a, e) with both words carried and every
 // index tested: small matrices, ragged ends of a range, and checks.
-template <bool HI>
-PERM3_FN int walk_range_direct(const RowW *__restrict__ R, int n, uint64_t a, uint64_t e, Masks mk)
+template <bool HI, typename RP>
+PERM3_FN int walk_range_direct(RP R, int n, uint64_t a, uint64_t e, Masks mk)
 {
     if (a >= e) return 0;
     const uint64_t g = a ^ (a >> 1);

@@ -229,11 +229,13 @@ def test_tuning_does_not_change_tallies():
     ref = P.perm_mod3_range_tally(A, 0, 1 << 33)
     saved = P.tuning_get()
     try:
-        for wps, bl, cl, tpw, dm in [(1, 4, 8, 1, 10), (2, 6, 12, 4, 12), (16, 5, 30, 64, 40), (8, 4, 20, 8, 33)]:
+        for wps, bl, cl, tpw, dm, st in [(1, 4, 8, 1, 10, 1), (2, 6, 12, 4, 12, 2), (16, 5, 30, 64, 40, 4),
+                                         (8, 4, 20, 8, 33, 2), (4, 5, 9, 2, 11, 4), (8, 6, 16, 16, 12, 1)]:
             t = P.perm_tuning()
             t.waves_per_simd, t.body_log, t.chunk_log_max, t.tasks_per_wave, t.direct_max_n = wps, bl, cl, tpw, dm
+            t.states_per_lane = st
             P.tuning_set(t)
-            assert P.perm_mod3_range_tally(A, 0, 1 << 33) == ref, (wps, bl, cl, tpw, dm)
+            assert P.perm_mod3_range_tally(A, 0, 1 << 33) == ref, (wps, bl, cl, tpw, dm, st)
             assert P.perm_mod3_range_tally(A, 12345, 1 << 22) == oracle.range_tally(A, 12345, 1 << 22)
     finally:
         P.tuning_set(saved)
