@@ -38,6 +38,23 @@ OPS_PER_TERM = 3.5
 PAPER_OPS_PER_TERM_2W = 14
 
 
+def measured_traffic():
+    """HBM bytes per walk launch from the committed counter passes (FETCH_SIZE and WRITE_SIZE,
+    each scaled by a 256 MiB copy); None once the kernel source differs from the profiled one."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_walk_36x36_counters.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    h = hashlib.sha256()
+    for name in ("perm3_walk.hpp", "perm3_kernels.hip"):
+        with open(os.path.join(ROOT, "paper_2407_20205_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return d["traffic_bytes_per_launch"] if h.hexdigest() == d.get("source_sha256") else None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -89,7 +106,7 @@ def bench_headline(P, W, torch, steps, warmup):
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T int32 lane-ops/s",
             "frac": achieved / PEAK_LANE_OPS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "ops_per_term": OPS_PER_TERM,
             "terms_per_launch": terms,
             "kernel": "k_walk<5,1>",
@@ -109,7 +126,7 @@ def packed_batch(P, W, torch, b):
             torch.from_numpy(b.ns.copy()).to(dev))
 
 
-def bench_batch(P, W, torch, reps):
+def bench_batch(P, W, torch, reps, baseline=True):
     b = W.batch_uniform()
     terms = int(sum((1 << int(n)) - 1 for n in b.ns))
     planes, row_off, ns = packed_batch(P, W, torch, b)
@@ -129,6 +146,16 @@ def bench_batch(P, W, torch, reps):
     h = hist.cpu().numpy().reshape(64, 3) // reps
     per_n = {int(n): [int(x) for x in h[n]] for n in range(12, 29)}
 
+    result = {
+        "workload": "8192 matrices, n uniform on 12..28, uniform entries, packed (mag, sgn) uint64 planes",
+        "matrices_per_s": b.count / sec,
+        "terms_per_s": terms / sec,
+        "ms_per_batch": 1e3 * sec,
+        "hist_per_n": per_n,
+        "zero_fraction": float(np.mean(res == 0)),
+    }
+    if not baseline:
+        return result
     # baseline: one launch sequence per matrix on the same GPU, no graphs
     L = P.lib()
     saved = P.tuning_get()
@@ -150,17 +177,70 @@ def bench_batch(P, W, torch, reps):
     sec1 = time.perf_counter() - t0
     P.tuning_set(saved)
     same = bool(np.array_equal(out1.cpu().numpy(), res))
-    return {
-        "workload": "8192 matrices, n uniform on 12..28, uniform entries, packed (mag, sgn) uint64 planes",
-        "matrices_per_s": b.count / sec,
-        "terms_per_s": terms / sec,
-        "ms_per_batch": 1e3 * sec,
-        "hist_per_n": per_n,
-        "zero_fraction": float(np.mean(res == 0)),
-        "baseline_one_launch_per_matrix": {"matrices_per_s": b.count / sec1, "ms": 1e3 * sec1,
-                                           "results_identical": same},
-        "speedup_vs_baseline": sec1 / sec,
-    }
+    result["baseline_one_launch_per_matrix"] = {"matrices_per_s": b.count / sec1, "ms": 1e3 * sec1,
+                                                "results_identical": same}
+    result["speedup_vs_baseline"] = sec1 / sec
+    return result
+
+
+# ------------------------------------------------------------------ single 20 x 20 (latency)
+
+def bench_single20(P, W, torch, reps=200):
+    """End-to-end latency of one 20x20 matrix resident in HBM (2^20 terms: launch-bound)."""
+    A = W.single_20()
+    dev = torch.device("cuda", 0)
+    mats = torch.from_numpy(A.reshape(-1).copy()).to(dev)
+    offs = torch.zeros(1, dtype=torch.int64, device=dev)
+    ns = torch.full((1,), 20, dtype=torch.int32, device=dev)
+    out = torch.zeros(1, dtype=torch.uint8, device=dev)
+    stream = torch.cuda.current_stream()
+    for _ in range(5):
+        P.perm_mod3_batch_dev(mats, offs, ns, out, None, stream)
+    torch.cuda.synchronize()
+    lat = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        P.perm_mod3_batch_dev(mats, offs, ns, out, None, stream)
+        stream.synchronize()
+        lat.append(time.perf_counter() - t0)
+    return {"workload": "one 20x20 uniform matrix resident in HBM, graph replay, synchronised each call",
+            "p50_us": 1e6 * pct(lat, 50), "p99_us": 1e6 * pct(lat, 99),
+            "terms_per_s": ((1 << 20) - 1) / pct(lat, 50), "result": int(out.item())}
+
+
+# ------------------------------------------------------------------ large and sparse
+
+def bench_large(P, W, torch):
+    """One 44x44 uniform matrix, then 64 matrices 40x40 with P(0) = 0.6 in one launch."""
+    big, sp = W.large_sparse()
+    dev = torch.device("cuda", 0)
+    mats = torch.from_numpy(big.reshape(-1).copy()).to(dev)
+    offs = torch.zeros(1, dtype=torch.int64, device=dev)
+    ns = torch.full((1,), 44, dtype=torch.int32, device=dev)
+    out = torch.zeros(1, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.perm_mod3_batch_dev(mats, offs, ns, out)
+    torch.cuda.synchronize()
+    t44 = time.perf_counter() - t0
+    r44 = int(out.item())
+    buf, o = sp.flat()
+    smats = torch.from_numpy(buf).to(dev)
+    soffs = torch.from_numpy(o[:-1].copy()).to(dev)
+    sns = torch.from_numpy(sp.ns.copy()).to(dev)
+    sout = torch.zeros(sp.count, dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P.perm_mod3_batch_dev(smats, soffs, sns, sout)
+    torch.cuda.synchronize()
+    t40 = time.perf_counter() - t0
+    terms44 = (1 << 44) - 1
+    terms40 = sp.count * ((1 << 40) - 1)
+    return {"workload": "one 44x44 uniform matrix; 64 matrices 40x40 with P(0)=0.6, P(1)=P(2)=0.2",
+            "n44_s": t44, "n44_terms_per_s": terms44 / t44, "n44_result": r44,
+            "sparse40_s": t40, "sparse40_terms_per_s": terms40 / t40,
+            "sparse40_matrices_per_s": sp.count / t40,
+            "sparse40_result_counts": [int((sout == v).sum().item()) for v in range(3)]}
 
 
 # ------------------------------------------------------------------ serving
@@ -271,10 +351,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["headline", "batch", "serve"], default=None)
+    ap.add_argument("--only", choices=["headline", "single20", "batch", "serve", "large"], default=None)
     ap.add_argument("--serve-count", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=None)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-baselines", action="store_true",
+                    help="skip the one-launch-per-matrix and FIFO baselines (for profiling)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a known-size kernel for "
                          "calibrating the FETCH_SIZE / WRITE_SIZE counters)")
@@ -318,13 +400,22 @@ def main():
         line["roofline"] = h["roofline"]
         line["headline_detail"] = {k: v for k, v in h.items() if k != "roofline"}
         line["vs_paper_one_core"] = h["terms_per_s"] / ((1 << 36) / 101.9)
+    if args.only in (None, "single20"):
+        s20 = bench_single20(P, W, torch)
+        log(f"single 20x20: p50 {s20['p50_us']:.1f} us, p99 {s20['p99_us']:.1f} us")
+        line["single20"] = s20
     if args.only in (None, "batch"):
-        bt = bench_batch(P, W, torch, reps=max(3, args.steps // 4))
-        log(f"batch: {bt['matrices_per_s']:.1f} matrices/s ({bt['speedup_vs_baseline']:.1f}x one-launch)")
+        bt = bench_batch(P, W, torch, reps=max(3, args.steps // 4), baseline=not args.no_baselines)
+        log(f"batch: {bt['matrices_per_s']:.1f} matrices/s ({bt.get('speedup_vs_baseline', 0):.1f}x one-launch)")
         line["batch"] = bt
     if args.only in (None, "serve"):
         cap = line.get("batch", {}).get("terms_per_s") or 8e12
         line["serve"] = bench_serve(P, W, torch, args.serve_rate, args.serve_count, cap)
+    if args.only in (None, "large"):
+        lg = bench_large(P, W, torch)
+        log(f"large: n=44 {lg['n44_s']:.3f} s ({lg['n44_terms_per_s']:.3e} terms/s), 64 sparse n=40 "
+            f"{lg['sparse40_s']:.3f} s ({lg['sparse40_terms_per_s']:.3e} terms/s)")
+        line["large"] = lg
     if args.only is None and not args.no_cpu:
         line["cpu_baseline"] = bench_cpu(W)
         log(f"cpu oracle: {line['cpu_baseline']['value']:.3e} terms/s on {line['cpu_baseline']['cores']} threads")
