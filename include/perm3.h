@@ -193,14 +193,17 @@ int32_t perm_server_destroy(perm_server *s);
  * Tuning, timing, device facts.
  */
 typedef struct {
-    int32_t waves_per_simd;   /* persistent waves per SIMD (1..16)                      */
-    int32_t body_log;         /* log2 of the unrolled Gray steps per block: 4, 5 or 6   */
-    int32_t chunk_log_max;    /* largest per-lane chunk, log2 Gray indices (8..30)      */
-    int32_t tasks_per_wave;   /* target tasks per persistent wave for large matrices    */
-    int32_t direct_max_n;     /* n at or below which every step is tested exactly      */
-    int32_t use_graphs;       /* 1: capture device-input calls into cached HIP graphs   */
-    int32_t states_per_lane;  /* chunks a lane walks side by side: 1, 2 or 4            */
-    int32_t reserved[1];
+    int32_t waves_per_simd;   /* persistent waves per SIMD (1..16)                        */
+    int32_t body_log;         /* log2 of the unrolled Gray steps per block, n > mid_max_n:
+                                 4, 5 or 6                                                  */
+    int32_t chunk_log_max;    /* largest per-lane chunk, log2 Gray indices (8..30)        */
+    int32_t tasks_per_wave;   /* target tasks per persistent wave                         */
+    int32_t direct_max_n;     /* n at or below which every step is tested exactly        */
+    int32_t use_graphs;       /* 1: capture device-input calls into cached HIP graphs     */
+    int32_t states_per_lane;  /* chunks a lane walks side by side: 1, 2 or 4              */
+    int32_t body_log_mid;     /* block log2 for direct_max_n < n <= mid_max_n: 4, 5 or 6  */
+    int32_t mid_max_n;        /* see body_log_mid                                         */
+    int32_t reserved[3];
 } perm_tuning;
 
 int32_t perm_tuning_get(perm_tuning *t);

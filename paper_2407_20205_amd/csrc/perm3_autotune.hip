@@ -75,6 +75,9 @@ extern "C" int32_t perm_autotune(int32_t n, int32_t budget_ms, perm_tuning *best
                     t.tasks_per_wave = tpw;
                     t.direct_max_n = dmx[di] < bl + 6 ? bl + 6 : dmx[di];
                     t.states_per_lane = st;
+                    // the candidate block length applies to matrices of this n
+                    if (n <= t.mid_max_n) t.body_log_mid = bl; else t.body_log = bl;
+                    if (t.direct_max_n < t.body_log_mid + 6) t.direct_max_n = t.body_log_mid + 6;
                     if (!tuning_valid(t)) continue;
                     c->tuning = t;
                     const uint8_t *As[1] = {A.data()};

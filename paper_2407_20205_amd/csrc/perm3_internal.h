@@ -23,6 +23,8 @@ struct MatMeta {
     int64_t row_base;   // first RowW of this matrix
     uint64_t lo, hi;    // Gray index range [lo, hi)
     uint64_t c_first;   // first chunk index (lo >> m)
+    int32_t ul;         // log2 of the unrolled block (4, 5 or 6)
+    int32_t pad;
 };
 
 // counters[] slots
@@ -34,6 +36,7 @@ struct PlanArgs {
     int32_t use_range;            // 1: matrix 0 walks [range_lo, range_hi) only (count == 1)
     uint64_t range_lo, range_hi;
     int32_t body_log, chunk_log_max, direct_max_n, direct_chunk_log_max;
+    int32_t body_log_mid, mid_max_n;  // block length for direct_max_n < n <= mid_max_n
     int32_t states_log;           // log2 of the chunks a lane carries side by side
     int32_t waves_total, tasks_per_wave;
     MatMeta *meta;
@@ -86,6 +89,8 @@ struct TickTask {
     int32_t mode;         // WalkMode (FAST or DIRECT)
     int32_t nchunks;      // valid chunks in this task (1..64)
     uint64_t c_first;     // first chunk of this task
+    int32_t ul;           // log2 of the unrolled block
+    int32_t pad;
 };
 
 struct SlotInfo {
@@ -115,8 +120,8 @@ struct FinishArgs {
 hipError_t launch_plan(const PlanArgs &a, hipStream_t st);
 hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st);
 hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st);
-hipError_t launch_walk(const WalkArgs &a, int body_log, int states, int grid_blocks, hipStream_t st);
-hipError_t launch_tick(const TickArgs &a, int body_log, int grid_blocks, hipStream_t st);
+hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st);
+hipError_t launch_tick(const TickArgs &a, int grid_blocks, hipStream_t st);
 hipError_t launch_finish(const FinishArgs &a, int max_fin, hipStream_t st);
 hipError_t launch_slot_pack(const uint8_t *A, int n, RowW *dst, hipStream_t st);
 hipError_t launch_bipedal_ops(const uint32_t *in, int count, uint32_t *out, hipStream_t st);

@@ -4,13 +4,13 @@
 //                 order (largest n first), row offsets; clears counters.
 //   k_pack_u8     phi of Section 2 on byte matrices, with validation.
 //   k_pack_planes accepts caller-packed (mag, sgn) uint64 planes, validated.
-//   k_walk<UL>    persistent waves pull 64-chunk tasks from an atomic queue,
+//   k_walk<S>     persistent waves pull 64-chunk tasks from an atomic queue,
 //                 walk them (perm3_walk.hpp), reduce each task's tally over the
 //                 wavefront with DPP, add it to the matrix's int64 tally; the
 //                 wave that completes a matrix's last task reduces it mod 3
 //                 (Section 3: s times (-1)^n, then cmod3) and counts it in the
 //                 per-n histogram.
-//   k_tick<UL>    the serving form of k_walk over an explicit task list.
+//   k_tick        the serving form of k_walk over an explicit task list.
 //   k_finish      serving: reduce finished slots' tallies mod 3.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -218,6 +218,8 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
         mt.lo = 0;
         mt.hi = 0;
         mt.c_first = 0;
+        mt.ul = a.body_log;
+        mt.pad = 0;
         a.tally[k] = 0;
         a.done[k] = 0;
         a.status[k] = valid ? 0 : 1;
@@ -233,13 +235,15 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
             mt.lo = lo;
             mt.hi = hi;
             const int slog = a.states_log;
-            const bool fast_ok = n >= a.body_log + 7 + slog && n > a.direct_max_n;
+            const int ul = n <= a.mid_max_n ? a.body_log_mid : a.body_log;
+            mt.ul = ul;
+            const bool fast_ok = n >= ul + 7 + slog && n > a.direct_max_n;
             int m;
             if (fast_ok) {
                 const int mmax = a.chunk_log_max < n - 6 - slog ? a.chunk_log_max : n - 6 - slog;
                 m = target_m;
                 if (m > mmax) m = mmax;
-                if (m < a.body_log + 1) m = a.body_log + 1;
+                if (m < ul + 1) m = ul + 1;
                 mt.mode = MODE_FAST;
             } else {
                 m = n - 6;
@@ -353,20 +357,42 @@ __global__ void __launch_bounds__(64) k_pack_planes(PackPlanesArgs a)
 
 // ------------------------------------------------------------------ walk
 
+// One task of one matrix: the lane's S chunks, with the matrix's block length.
 template <int UL, int S>
+__device__ __forceinline__ int walk_task(cptr<RowW> R, const MatMeta &mt, uint64_t c)
+{
+    StaticRows<UL> sr;
+    if (mt.mode == MODE_FAST) load_static_rows<UL>(R, sr);
+    return walk_lane_states<UL, S>(R, mt.n, mt.m, mt.mode, c, mt.lo, mt.hi, sr);
+}
+
+// The index of this wavefront in the grid (wave-uniform).
+__device__ __forceinline__ uint32_t wave_index()
+{
+    return blockIdx.x * (WALK_BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+}
+
+// Task scheduling shared by k_walk and k_tick: wave w first takes task w
+// with no atomic, then draws grid-size + counter; a wave whose first task is
+// past the end leaves at once, so small jobs touch the counter once per
+// active wave instead of once per launched wave.
+__device__ __forceinline__ uint32_t next_task(uint32_t *queue, uint32_t nwaves, int lane)
+{
+    uint32_t t = 0;
+    if (lane == 0) t = atomicAdd(queue, 1u);
+    return nwaves + __builtin_amdgcn_readfirstlane(t);
+}
+
+template <int S>
 __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t total = a.counters[CNT_TOTAL_TASKS];
-    for (;;) {
-        uint32_t tau = 0;
-        if (lane == 0) tau = atomicAdd(&a.counters[CNT_QUEUE], 1u);
-        tau = __builtin_amdgcn_readfirstlane(tau);
-        if (tau >= total) break;
-
+    const uint32_t nwaves = gridDim.x * (WALK_BLOCK / 64);
+    const cptr<uint32_t> task_start = to_const(a.task_start);
+    for (uint32_t tau = wave_index(); tau < total; tau = next_task(&a.counters[CNT_QUEUE], nwaves, lane)) {
         // position p in the order whose tasks contain tau: the largest p with
         // task_start[p] <= tau (matrices without tasks share their successor's start)
-        const cptr<uint32_t> task_start = to_const(a.task_start);
         int lo = 0, hi = a.count;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
@@ -379,10 +405,13 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
         int tally = 0;
         if (to_const(a.status)[k] == 0) {
             const cptr<RowW> R = to_const(a.rows) + mt.row_base;
-            StaticRows<UL> sr;
-            if (mt.mode == MODE_FAST) load_static_rows<UL>(R, sr);
             const uint64_t c = mt.c_first + (uint64_t)q * (64u * S) + (uint64_t)lane;
-            tally = walk_lane_states<UL, S>(R, mt.n, mt.m, mt.mode, c, mt.lo, mt.hi, sr);
+            if (mt.ul == 4)
+                tally = walk_task<4, S>(R, mt, c);
+            else if (mt.ul == 6)
+                tally = walk_task<6, S>(R, mt, c);
+            else
+                tally = walk_task<5, S>(R, mt, c);
         }
         const int sum = wave_sum(tally);
 
@@ -408,25 +437,30 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
 
 // ------------------------------------------------------------------ serving
 
-template <int UL>
 __global__ void __launch_bounds__(WALK_BLOCK) k_tick(TickArgs a)
 {
     const int lane = threadIdx.x & 63;
     const uint32_t total = *a.ntasks;
-    for (;;) {
-        uint32_t tau = 0;
-        if (lane == 0) tau = atomicAdd(a.queue, 1u);
-        tau = __builtin_amdgcn_readfirstlane(tau);
-        if (tau >= total) break;
+    const uint32_t nwaves = gridDim.x * (WALK_BLOCK / 64);
+    for (uint32_t tau = wave_index(); tau < total; tau = next_task(a.queue, nwaves, lane)) {
         const TickTask tk = load_const(a.tasks, tau);
         const SlotInfo si = load_const(a.slots, tk.slot);
         const cptr<RowW> R = to_const(a.rows) + si.row_base;
-        StaticRows<UL> sr;
-        if (tk.mode == MODE_FAST) load_static_rows<UL>(R, sr);
+        MatMeta mt;
+        mt.n = si.n;
+        mt.m = tk.m;
+        mt.mode = tk.mode;
+        mt.lo = 0;
+        mt.hi = 1ull << si.n;
         int tally = 0;
         if (lane < tk.nchunks) {
             const uint64_t c = tk.c_first + (uint64_t)lane;
-            tally = walk_lane<UL>(R, si.n, tk.m, tk.mode, c, 0, 1ull << si.n, sr);
+            if (tk.ul == 4)
+                tally = walk_task<4, 1>(R, mt, c);
+            else if (tk.ul == 6)
+                tally = walk_task<6, 1>(R, mt, c);
+            else
+                tally = walk_task<5, 1>(R, mt, c);
         }
         const int sum = wave_sum(tally);
         if (lane == 0 && sum != 0)
@@ -510,36 +544,20 @@ hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int UL>
-static void launch_walk_s(const WalkArgs &a, int states, int grid_blocks, hipStream_t st)
+hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st)
 {
     switch (states) {
-    case 1: hipLaunchKernelGGL((k_walk<UL, 1>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_walk<UL, 2>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
-    default: hipLaunchKernelGGL((k_walk<UL, 4>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
-    }
-}
-
-hipError_t launch_walk(const WalkArgs &a, int body_log, int states, int grid_blocks, hipStream_t st)
-{
-    if (states != 1 && states != 2 && states != 4) return hipErrorInvalidValue;
-    switch (body_log) {
-    case 4: launch_walk_s<4>(a, states, grid_blocks, st); break;
-    case 5: launch_walk_s<5>(a, states, grid_blocks, st); break;
-    case 6: launch_walk_s<6>(a, states, grid_blocks, st); break;
+    case 1: hipLaunchKernelGGL((k_walk<1>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    case 2: hipLaunchKernelGGL((k_walk<2>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_walk<4>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_tick(const TickArgs &a, int body_log, int grid_blocks, hipStream_t st)
+hipError_t launch_tick(const TickArgs &a, int grid_blocks, hipStream_t st)
 {
-    switch (body_log) {
-    case 4: hipLaunchKernelGGL(k_tick<4>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
-    case 5: hipLaunchKernelGGL(k_tick<5>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
-    case 6: hipLaunchKernelGGL(k_tick<6>, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
-    default: return hipErrorInvalidValue;
-    }
+    hipLaunchKernelGGL(k_tick, dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a);
     return hipGetLastError();
 }
 

@@ -69,6 +69,8 @@ perm_tuning default_tuning()
     t.direct_max_n = 16;
     t.use_graphs = 1;
     t.states_per_lane = 1;
+    t.body_log_mid = 4;
+    t.mid_max_n = 31;
     return t;
 }
 
@@ -78,7 +80,9 @@ bool tuning_valid(const perm_tuning &t)
            t.chunk_log_max >= 8 && t.chunk_log_max <= 30 && t.tasks_per_wave >= 1 &&
            t.tasks_per_wave <= 1024 && t.direct_max_n >= t.body_log + 6 && t.direct_max_n <= 63 &&
            (t.use_graphs == 0 || t.use_graphs == 1) &&
-           (t.states_per_lane == 1 || t.states_per_lane == 2 || t.states_per_lane == 4);
+           (t.states_per_lane == 1 || t.states_per_lane == 2 || t.states_per_lane == 4) &&
+           t.body_log_mid >= 4 && t.body_log_mid <= 6 && t.mid_max_n >= 0 && t.mid_max_n <= 63 &&
+           t.direct_max_n >= t.body_log_mid + 6;
 }
 
 // ------------------------------------------------------------------ context
@@ -227,6 +231,8 @@ PlanArgs Context::plan_args(const int32_t *ns_dev, int32_t count, uint8_t *out_d
     a.chunk_log_max = tuning.chunk_log_max;
     a.direct_max_n = tuning.direct_max_n;
     a.direct_chunk_log_max = 10;
+    a.body_log_mid = tuning.body_log_mid;
+    a.mid_max_n = tuning.mid_max_n;
     a.states_log = tuning.states_per_lane == 4 ? 2 : (tuning.states_per_lane == 2 ? 1 : 0);
     a.waves_total = waves_total();
     a.tasks_per_wave = tuning.tasks_per_wave;
@@ -288,8 +294,7 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
         HIP_TRY(launch_pack_planes(pk, st));
     }
     if (timed) HIP_TRY(hipEventRecord(ev_walk0, st));
-    HIP_TRY(launch_walk(walk_args(L.count, L.out_dev, L.hist_dev), tuning.body_log, tuning.states_per_lane,
-                        grid_blocks(), st));
+    HIP_TRY(launch_walk(walk_args(L.count, L.out_dev, L.hist_dev), tuning.states_per_lane, grid_blocks(), st));
     if (timed) {
         HIP_TRY(hipEventRecord(ev_walk1, st));
         HIP_TRY(hipEventRecord(ev_all1, st));
@@ -319,8 +324,7 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
                  (uintptr_t)L.hist_dev,
                  (uintptr_t)st,
                  L.count,
-                 tuning.waves_per_simd * 1000000 + tuning.body_log * 100000 + tuning.chunk_log_max * 1000 +
-                     tuning.tasks_per_wave * 100 + tuning.direct_max_n + tuning.states_per_lane * 10000000};
+                 0};   // tuning changes drop every cached graph
     auto it = graphs.find(key);
     if (it == graphs.end()) {
         if (graphs.size() >= 32) drop_graphs();

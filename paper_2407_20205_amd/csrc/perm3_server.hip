@@ -53,7 +53,7 @@ struct Slot {
     bool used = false;
     Request req;
     uint64_t t_admit = 0;
-    int32_t m = 0, mode = MODE_DIRECT;
+    int32_t m = 0, mode = MODE_DIRECT, ul = 5;
     uint64_t next_chunk = 0, nchunks = 0;
     uint64_t seq = 0;
     uint64_t remaining() const { return (nchunks - next_chunk) << m; }
@@ -189,13 +189,14 @@ void perm_server::admit(std::deque<Request> &incoming, std::vector<int> &to_pack
         sl.t_admit = now_ns();
         sl.seq = seq++;
         const int n = sl.req.n;
-        if (n > tuning.direct_max_n && n >= tuning.body_log + 7) {
+        sl.ul = n <= tuning.mid_max_n ? tuning.body_log_mid : tuning.body_log;
+        if (n > tuning.direct_max_n && n >= sl.ul + 7) {
             sl.mode = MODE_FAST;
             // chunks small enough that one quantum spreads over many waves
             int m = 14;
             const int mmax = std::min(tuning.chunk_log_max, n - 6);
             if (m > mmax) m = mmax;
-            if (m < tuning.body_log + 1) m = tuning.body_log + 1;
+            if (m < sl.ul + 1) m = sl.ul + 1;
             sl.m = m;
         } else {
             sl.mode = MODE_DIRECT;
@@ -251,6 +252,8 @@ int32_t perm_server::tick(std::vector<perm_done> &finished)
             t.mode = sl.mode;
             t.nchunks = (int32_t)k;
             t.c_first = c;
+            t.ul = sl.ul;
+            t.pad = 0;
             c += k;
         }
         sl.next_chunk = end;
@@ -277,7 +280,7 @@ int32_t perm_server::tick(std::vector<perm_done> &finished)
     const int need = (int)((nt + 3) / 4);
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
-    SRV_TRY(launch_tick(ta, tuning.body_log, blocks, stream));
+    SRV_TRY(launch_tick(ta, blocks, stream));
     FinishArgs fa;
     fa.fin_slots = d_fin;
     fa.nfin = d_counts + 1;

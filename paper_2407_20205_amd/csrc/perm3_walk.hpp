@@ -117,14 +117,11 @@ PERM3_FN uint32_t to_vgpr(uint32_t x)
 #endif
 
 // Exact re-walk of Gray indices ia+1 .. ib (ia itself already counted) for
-// the lanes whose block held a candidate: the low words are re-seeded at ia
-// from the Gray state and stepped; the high words are formed only where the
-// low words pass.  Lean on registers, so it can sit inside the walk loop.
+// the lanes whose block held a candidate, from the low words (ml, sl) of the
+// subset sum at ia; the high words are formed only where the low words pass.
 template <typename RP>
-PERM3_FN int rewalk_exact(RP R, int n, uint64_t ia, uint64_t ib, Masks mk)
+PERM3_FN int rewalk_exact(RP R, int n, uint64_t ia, uint64_t ib, uint32_t ml, uint32_t sl, Masks mk)
 {
-    uint32_t ml, sl;
-    seed_lo(R, n, ia, ml, sl);
     int tally = 0;
     for (uint64_t i = ia + 1; i <= ib; ++i) {
         const int t = __builtin_ctzll(i);
@@ -155,7 +152,7 @@ PERM3_FN int rewalk_exact(RP R, int n, uint64_t ia, uint64_t ib, Masks mk)
 // each low mag word is <= mk.lo, so the block's maximum equals mk.lo exactly
 // when some index in it has all its low columns non-zero (one 3-input max
 // per two states, or per two steps when S = 1).  Only then is the block
-// walked again exactly (rewalk_exact from the block's first index).
+// walked again exactly (rewalk_exact from the state saved at its first index).
 template <int UL, int S, typename RP>
 PERM3_FN int walk_chunks_fast(RP R, int n, int m, uint64_t c, Masks mk, const StaticRows<UL> &sr)
 {
@@ -188,6 +185,12 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, uint64_t c, Masks mk, const St
             const bool leave = (jb >> (tb + 1 - UL)) & 1u;
             const uint32_t bm = PERM3_TO_VGPR(inner ? R[tb].m_lo : 0u);
             const uint32_t bs = PERM3_TO_VGPR(inner ? (leave ? R[tb].sn_lo : R[tb].s_lo) : 0u);
+            uint32_t m0[S], s0[S];
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                m0[q] = ml[q];
+                s0[q] = sl[q];
+            }
             uint32_t acc = 0;
 #pragma unroll
             for (int k = 1; k <= (int)U; ++k) {
@@ -221,7 +224,7 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, uint64_t c, Masks mk, const St
 #pragma unroll
                 for (int q = 0; q < S; ++q) {
                     const uint64_t i0 = (c + 64u * (uint64_t)q) << m;
-                    tally += rewalk_exact(R, n, i0 + b * U, i0 + last, mk);
+                    tally += rewalk_exact(R, n, i0 + b * U, i0 + last, m0[q], s0[q], mk);
                 }
             }
         }

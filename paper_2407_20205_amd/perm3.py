@@ -61,7 +61,8 @@ class perm_tuning(ctypes.Structure):
     _fields_ = [("waves_per_simd", ctypes.c_int32), ("body_log", ctypes.c_int32),
                 ("chunk_log_max", ctypes.c_int32), ("tasks_per_wave", ctypes.c_int32),
                 ("direct_max_n", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
-                ("states_per_lane", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("states_per_lane", ctypes.c_int32), ("body_log_mid", ctypes.c_int32),
+                ("mid_max_n", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

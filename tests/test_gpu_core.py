@@ -234,6 +234,7 @@ def test_tuning_does_not_change_tallies():
             t = P.perm_tuning()
             t.waves_per_simd, t.body_log, t.chunk_log_max, t.tasks_per_wave, t.direct_max_n = wps, bl, cl, tpw, dm
             t.states_per_lane = st
+            t.body_log_mid, t.mid_max_n = (min(6, dm - 6), 40) if bl == 4 else (4, 20)
             P.tuning_set(t)
             assert P.perm_mod3_range_tally(A, 0, 1 << 33) == ref, (wps, bl, cl, tpw, dm, st)
             assert P.perm_mod3_range_tally(A, 12345, 1 << 22) == oracle.range_tally(A, 12345, 1 << 22)
