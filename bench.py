@@ -243,6 +243,25 @@ def bench_large(P, W, torch):
             "sparse40_result_counts": [int((sout == v).sum().item()) for v in range(3)]}
 
 
+# ------------------------------------------------------------------ Pi_50 (Section 3.1)
+
+def bench_pi50(P, W, shards=64, ckdir=None):
+    """perm(Pi_50) mod 3, both readings of the matrix, as a sharded and checkpointed run."""
+    from paper_2407_20205_amd import longrun
+    out = {}
+    for reading in ("rows", "formula"):
+        A = W.pi_matrix(50, reading)
+        ck = os.path.join(ckdir, f"pi50_{reading}.json") if ckdir else None
+        t0 = time.perf_counter()
+        r = longrun.perm_mod3_sharded(A, shards, checkpoint=ck, log=log)
+        sec = time.perf_counter() - t0
+        out[reading] = {"perm_mod3": int(r), "as_centred": {0: 0, 1: 1, 2: -1}[int(r)], "seconds": sec,
+                        "terms_per_s": ((1 << 50) - 1) / sec, "matrix_sha256": longrun.matrix_hash(A)}
+        log(f"Pi_50 ({reading}): perm = {r} (mod 3) in {sec:.1f} s")
+    out["paper"] = "perm(Pi_50) = -1 (mod 3) after 832 hours of parallel computation (Section 3.1)"
+    return out
+
+
 # ------------------------------------------------------------------ serving
 
 def expected_work(W):
@@ -351,7 +370,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["headline", "single20", "batch", "serve", "large"], default=None)
+    ap.add_argument("--only", choices=["headline", "single20", "batch", "serve", "large", "pi50"], default=None)
+    ap.add_argument("--checkpoint-dir", default=None, help="checkpoint files of the sharded Pi_50 run")
     ap.add_argument("--serve-count", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=None)
     ap.add_argument("--no-cpu", action="store_true")
@@ -416,6 +436,8 @@ def main():
         log(f"large: n=44 {lg['n44_s']:.3f} s ({lg['n44_terms_per_s']:.3e} terms/s), 64 sparse n=40 "
             f"{lg['sparse40_s']:.3f} s ({lg['sparse40_terms_per_s']:.3e} terms/s)")
         line["large"] = lg
+    if args.only == "pi50":
+        line["pi50"] = bench_pi50(P, W, ckdir=args.checkpoint_dir)
     if args.only is None and not args.no_cpu:
         line["cpu_baseline"] = bench_cpu(W)
         log(f"cpu oracle: {line['cpu_baseline']['value']:.3e} terms/s on {line['cpu_baseline']['cores']} threads")

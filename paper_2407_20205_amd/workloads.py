@@ -183,3 +183,46 @@ def hidden_block_diagonal(sizes, seed: int) -> tuple[np.ndarray, list]:
     P = g.permutation(n)
     Q = g.permutation(n)
     return np.ascontiguousarray(M[P][:, Q]), blocks
+
+
+# ---- the digits-of-pi matrix of Section 3.1 ---------------------------------
+
+def _arctan_inv(x: int, unity: int) -> int:
+    """arctan(1/x) * unity by its alternating power series, in integers."""
+    total = term = unity // x
+    x2 = x * x
+    k = 1
+    while term:
+        term //= x2
+        k += 2
+        total += -(term // k) if (k // 2) % 2 else term // k
+    return total
+
+
+def pi_digits(count: int) -> str:
+    """The first ``count`` decimal digits of pi ("31415..."), from Machin's formula
+    pi = 16 arctan(1/5) - 4 arctan(1/239), with 10 guard digits."""
+    guard = 10
+    unity = 10 ** (count + guard)
+    pi = 16 * _arctan_inv(5, unity) - 4 * _arctan_inv(239, unity)
+    return str(pi)[:count]
+
+
+def pi_matrix(n: int, reading: str = "rows") -> np.ndarray:
+    """Pi_n: an n x n matrix of decimal digits of pi reduced mod 3 (so entries are in
+    {0, 1, 2}, 2 standing for -1).
+
+    reading "rows": row i (0-based) holds digits n*i + 1 .. n*i + n (1-based digit
+    positions), i.e. the first row is the first n digits, as the prose says.
+    reading "formula": entry (i, j) (1-based) is digit (n-1)*i + j taken literally
+    with i counted from 0, so consecutive rows share one digit.
+    """
+    if reading == "rows":
+        d = pi_digits(n * n)
+        idx = [[n * i + j for j in range(n)] for i in range(n)]
+    elif reading == "formula":
+        d = pi_digits((n - 1) * (n - 1) + n)
+        idx = [[(n - 1) * i + j for j in range(n)] for i in range(n)]
+    else:
+        raise ValueError(reading)
+    return np.array([[int(d[k]) % 3 for k in row] for row in idx], dtype=np.uint8)
