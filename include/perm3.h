@@ -134,6 +134,28 @@ int32_t perm_mod3_batch_packed(const uint64_t *planes_dev, const int64_t *row_of
 int32_t perm_mod3_pack(const uint8_t *A, int32_t n, uint64_t *planes);
 
 /* --------------------------------------------------------------------------
+ * Census: how many matrices have perm 0, 1 and -1, over matrices made on the
+ * device (the exact counts of Table 3 and the Monte Carlo study of Table 4).
+ *
+ * generator PERM_GEN_ENUMERATE: matrix t (first <= t < first + count) has
+ *   entry k (row-major) equal to the k-th base-3 digit of t, least significant
+ *   first; t = 0 .. 3^(n*n) - 1 lists every n x n matrix over F_3 once.
+ *   Requires n <= 6 and first + count <= 3^(n*n).
+ * generator PERM_GEN_SPLITMIX: entry k of matrix t is floor(3 x / 2^64) for x
+ *   the (t*n*n + k + 1)-th output of SplitMix64 seeded with `key` (Steele, Lea
+ *   and Flood 2014: state key + q * 0x9E3779B97F4A7C15, then its mixing
+ *   function), i.e. iid uniform entries.
+ * counts: host uint64[3], receives the number of matrices with perm mod 3
+ * equal to 0, 1 and 2.  1 <= n <= 63.  Synchronous.  Small n walk one matrix
+ * per lane; larger n are generated into device memory in chunks and walked by
+ * the batch path.
+ */
+#define PERM_GEN_ENUMERATE 0
+#define PERM_GEN_SPLITMIX  1
+int32_t perm_mod3_census(int32_t n, int32_t generator, uint64_t key, uint64_t first, uint64_t count,
+                         uint64_t *counts);
+
+/* --------------------------------------------------------------------------
  * Serving: a request loop with continuous batching.
  *
  * Requests (one matrix each) are admitted into device-resident slots while

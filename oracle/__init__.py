@@ -65,6 +65,11 @@ def lib():
         L.oracle_perm_mod3.restype = ctypes.c_int
         L.oracle_count_by_value.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_uint64)]
         L.oracle_count_by_value.restype = ctypes.c_int
+        L.oracle_census.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                    ctypes.POINTER(ctypes.c_uint64)]
+        L.oracle_census.restype = ctypes.c_int
+        L.oracle_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        L.oracle_splitmix64.restype = ctypes.c_uint64
         _lib = L
     return _lib
 
@@ -121,6 +126,20 @@ def count_by_value(n: int) -> tuple[int, int, int]:
     if lib().oracle_count_by_value(n, c) != 0:
         raise ValueError("n must be in 1..4")
     return int(c[0]), int(c[1]), int(c[2])
+
+
+def census(n: int, generator: int, key: int, first: int, count: int) -> tuple[int, int, int]:
+    """Counts of perm mod 3 = 0, 1, 2 over generated matrices (0: base-3 enumeration of the
+    matrix index, 1: SplitMix64 draws), matrices first .. first + count - 1; n <= 63."""
+    c = (ctypes.c_uint64 * 3)()
+    if lib().oracle_census(n, generator, key, first, count, c) != 0:
+        raise ValueError("bad census arguments")
+    return int(c[0]), int(c[1]), int(c[2])
+
+
+def splitmix64(key: int, q: int) -> int:
+    """The q-th output (q >= 1) of SplitMix64 seeded with key."""
+    return int(lib().oracle_splitmix64(key, q))
 
 
 def signed(A) -> list[list[int]]:

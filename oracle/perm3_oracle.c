@@ -233,3 +233,45 @@ int oracle_count_by_value(int n, uint64_t counts[3])
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Census over generated matrices (the counts of Table 3, the Monte Carlo
+ * study of Table 4).  Matrix t, entry k (row-major):
+ *   generator 0: the k-th base-3 digit of t, least significant first;
+ *   generator 1: floor(3 x / 2^64) for x the (t*n*n + k + 1)-th output of
+ *                SplitMix64 seeded with key (state key + q * gamma, gamma =
+ *                0x9E3779B97F4A7C15, then the generator's mixing function). */
+
+static uint64_t splitmix64_output(uint64_t key, uint64_t q)
+{
+    uint64_t z = key + q * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+uint64_t oracle_splitmix64(uint64_t key, uint64_t q) { return splitmix64_output(key, q); }
+
+int oracle_census(int n, int generator, uint64_t key, uint64_t first, uint64_t count, uint64_t counts[3])
+{
+    counts[0] = counts[1] = counts[2] = 0;
+    if (n < 1 || n > ORACLE_MAX_N || (generator != 0 && generator != 1)) return -1;
+    uint8_t A[ORACLE_MAX_N * ORACLE_MAX_N];
+    const int cells = n * n;
+    for (uint64_t t = first; t < first + count; ++t) {
+        uint64_t rest = t;
+        for (int k = 0; k < cells; ++k) {
+            if (generator == 0) {
+                A[k] = (uint8_t)(rest % 3);
+                rest /= 3;
+            } else {
+                unsigned __int128 x = splitmix64_output(key, t * (uint64_t)cells + (uint64_t)k + 1);
+                A[k] = (uint8_t)((x * 3) >> 64);
+            }
+        }
+        int r = oracle_perm_mod3(A, n, 1);
+        if (r < 0) return -1;
+        counts[r] += 1;
+    }
+    return 0;
+}

@@ -1,0 +1,147 @@
+// Census kernels: perm mod 3 over many matrices made on the device.
+//
+// Generators (a matrix is n x n bytes in {0,1,2}, entry k in row-major order):
+//   GEN_ENUMERATE  matrix t has entry k = the k-th base-3 digit of t (least
+//                  significant first), so t = 0 .. 3^(n*n)-1 lists every
+//                  matrix over F_3 once (the exact counts z(n) of Table 3);
+//   GEN_SPLITMIX   entry k of matrix t is floor(3 x / 2^64) for x the
+//                  (t*n*n + k + 1)-th output of SplitMix64 seeded with `key`
+//                  (Steele, Lea and Flood, 2014): state s_q = key + q * 0x9E3779B97F4A7C15,
+//                  output = mix(s_q) (uniform random matrices, Table 4).
+//
+// k_census_lanes: one matrix per lane for n <= CENSUS_LANE_MAX_N.  The lane
+// walks all 2^n - 1 Gray steps of its matrix with every index tested (the
+// rows sit in LDS, one column of words per lane; all lanes flip the same row
+// at the same step), forms ((-1)^n T) mod 3, and the wave counts results 0,
+// 1 and 2 with ballots.  Larger n: k_generate writes the matrices and the
+// batch walk takes them.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "perm3_internal.h"
+#include "perm3_walk.hpp"
+
+namespace perm3 {
+
+__device__ __forceinline__ uint64_t splitmix_out(uint64_t key, uint64_t q)
+{
+    uint64_t z = key + q * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// floor(3 x / 2^64): the high word of 3x = 2x + x
+__device__ __forceinline__ uint32_t trit_of(uint64_t x)
+{
+    const uint64_t lo2 = x << 1;
+    const uint64_t sum = lo2 + x;
+    return (uint32_t)(x >> 63) + (sum < x ? 1u : 0u);
+}
+
+// Entry k of matrix t.  For enumeration the caller passes the running quotient
+// (t / 3^k) and gets the next one back.
+__device__ __forceinline__ uint32_t census_entry(int gen, uint64_t key, uint64_t t, int nn, int k, uint64_t &rest)
+{
+    if (gen == GEN_ENUMERATE) {
+        const uint64_t q = rest / 3u;
+        const uint32_t d = (uint32_t)(rest - 3u * q);
+        rest = q;
+        return d;
+    }
+    return trit_of(splitmix_out(key, t * (uint64_t)nn + (uint64_t)k + 1u));
+}
+
+constexpr int CENSUS_BLOCK = 256;
+
+__global__ void __launch_bounds__(CENSUS_BLOCK) k_census_lanes(CensusArgs a)
+{
+    __shared__ uint32_t s_m[CENSUS_LANE_MAX_N][CENSUS_BLOCK];
+    __shared__ uint32_t s_s[CENSUS_LANE_MAX_N][CENSUS_BLOCK];
+    const int n = a.n;
+    const int nn = n * n;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const uint64_t lanes = (uint64_t)gridDim.x * CENSUS_BLOCK;
+    const uint64_t rounds = (a.count + lanes - 1) / lanes;
+    const uint32_t mask = (1u << n) - 1u;
+    unsigned long long c0 = 0, c1 = 0, c2 = 0;
+    for (uint64_t r = 0; r < rounds; ++r) {
+        const uint64_t idx = r * lanes + (uint64_t)blockIdx.x * CENSUS_BLOCK + tid;
+        const bool active = idx < a.count;
+        const uint64_t t = a.first + idx;
+        // the lane's matrix, packed by phi: element j of row i at bit n-1-j
+        uint64_t rest = t;
+        for (int i = 0; i < n; ++i) {
+            uint32_t mag = 0, sgn = 0;
+            for (int j = 0; j < n; ++j) {
+                const uint32_t v = census_entry(a.gen, a.key, t, nn, i * n + j, rest);
+                const uint32_t bit = 1u << (n - 1 - j);
+                mag |= v != 0 ? bit : 0u;
+                sgn |= v == 2 ? bit : 0u;
+            }
+            s_m[i][tid] = mag;
+            s_s[i][tid] = sgn;
+        }
+        // Gray walk over all subsets from the empty one: every index tested
+        uint32_t ml = 0, sl = 0;
+        int tally = 0;
+        const uint32_t steps = (1u << n) - 1u;
+        for (uint32_t i = 1; i <= steps; ++i) {
+            const int tr = __builtin_ctz(i);
+            const uint32_t rm = s_m[tr][tid], rs0 = s_s[tr][tid];
+            const bool leave = (i >> (tr + 1)) & 1u;
+            bip_add(ml, sl, rm, leave ? (rs0 ^ rm) : rs0);
+            if (ml == mask) {
+                const int par = (__builtin_popcount(sl) + (int)(i & 1u)) & 1;
+                tally += par ? -1 : 1;
+            }
+        }
+        const int p = (n & 1) ? -tally : tally;
+        int res = p % 3;
+        if (res < 0) res += 3;
+        const unsigned long long b0 = __ballot(active && res == 0);
+        const unsigned long long b1 = __ballot(active && res == 1);
+        const unsigned long long b2 = __ballot(active && res == 2);
+        if (lane == 0) {
+            c0 += __popcll(b0);
+            c1 += __popcll(b1);
+            c2 += __popcll(b2);
+        }
+    }
+    if (lane == 0) {
+        if (c0) atomicAdd(&a.counts[0], c0);
+        if (c1) atomicAdd(&a.counts[1], c1);
+        if (c2) atomicAdd(&a.counts[2], c2);
+    }
+}
+
+__global__ void __launch_bounds__(256) k_generate(GenArgs a)
+{
+    const uint32_t idx = blockIdx.x * 256 + threadIdx.x;
+    if (idx >= a.count) return;
+    const int n = a.n;
+    const int nn = n * n;
+    const uint64_t t = a.first + idx;
+    uint64_t rest = t;
+    uint8_t *dst = a.mats + (uint64_t)idx * nn;
+    for (int k = 0; k < nn; ++k) dst[k] = (uint8_t)census_entry(a.gen, a.key, t, nn, k, rest);
+    a.offs[idx] = (int64_t)idx * nn;
+    a.ns[idx] = n;
+}
+
+hipError_t launch_census_lanes(const CensusArgs &a, int grid_blocks, hipStream_t st)
+{
+    if (a.n < 1 || a.n > CENSUS_LANE_MAX_N) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_census_lanes, dim3(grid_blocks), dim3(CENSUS_BLOCK), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_generate(const GenArgs &a, hipStream_t st)
+{
+    if (a.count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_generate, dim3((a.count + 255) / 256), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+}  // namespace perm3

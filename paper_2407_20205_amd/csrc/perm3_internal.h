@@ -129,3 +129,35 @@ hipError_t launch_bipedal_ops(const uint32_t *in, int count, uint32_t *out, hipS
 constexpr int WALK_BLOCK = 256;   // 4 waves, one per SIMD
 
 }  // namespace perm3
+
+namespace perm3 {
+
+// Matrices generated on the device for a census (perm_mod3_census).
+enum CensusGen : int32_t { GEN_ENUMERATE = 0, GEN_SPLITMIX = 1 };
+
+struct CensusArgs {
+    int32_t n;
+    int32_t gen;
+    uint64_t key;
+    uint64_t first;                 // first matrix index
+    uint64_t count;                 // matrices
+    unsigned long long *counts;     // [3] perm = 0, 1, 2 (added to)
+};
+
+struct GenArgs {                    // write matrices first .. first+count-1 as bytes
+    int32_t n;
+    int32_t gen;
+    uint64_t key;
+    uint64_t first;
+    uint32_t count;
+    uint8_t *mats;                  // count * n * n bytes
+    int64_t *offs;                  // [count]
+    int32_t *ns;                    // [count]
+};
+
+constexpr int CENSUS_LANE_MAX_N = 14;   // one matrix per lane up to this n
+
+hipError_t launch_census_lanes(const CensusArgs &a, int grid_blocks, hipStream_t st);
+hipError_t launch_generate(const GenArgs &a, hipStream_t st);
+
+}  // namespace perm3

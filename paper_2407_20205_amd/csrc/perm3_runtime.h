@@ -66,7 +66,7 @@ struct Context {
     std::mutex mu;
 
     DevBuf meta, order, task_start, tally, done, status, counters, rowbuf;
-    DevBuf d_stage, d_out;
+    DevBuf d_stage, d_out, d_census, d_gen;
     HostBuf h_stage;
 
     std::map<GraphKey, hipGraphExec_t> graphs;

@@ -595,6 +595,89 @@ int32_t perm_mod3_pack(const uint8_t *A, int32_t n, uint64_t *planes)
     return PERM_OK;
 }
 
+int32_t perm_mod3_census(int32_t n, int32_t generator, uint64_t key, uint64_t first, uint64_t count,
+                         uint64_t *counts)
+{
+    set_error_index(-1);
+    if (!counts) return set_error(PERM_EINVAL, "null counts pointer");
+    if (n < 1 || n > PERM_MAX_N) return set_error(PERM_EINVAL, "n = %d is outside [1, %d]", n, PERM_MAX_N);
+    if (generator != PERM_GEN_ENUMERATE && generator != PERM_GEN_SPLITMIX)
+        return set_error(PERM_EINVAL, "unknown generator %d", generator);
+    if (generator == PERM_GEN_ENUMERATE) {
+        if (n > 6) return set_error(PERM_EINVAL, "enumeration needs n <= 6");
+        uint64_t total = 1;
+        for (int k = 0; k < n * n; ++k) total *= 3u;
+        if (first > total || count > total - first)
+            return set_error(PERM_EINVAL, "matrices [%llu, +%llu) exceed 3^%d", (unsigned long long)first,
+                             (unsigned long long)count, n * n);
+    }
+    counts[0] = counts[1] = counts[2] = 0;
+    if (count == 0) return PERM_OK;
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    hipStream_t st = c->stream;
+    if ((rc = c->join(st))) return rc;
+    HIP_TRY(c->d_census.reserve(64 * 3 * sizeof(uint64_t)));
+    unsigned long long *dcounts = (unsigned long long *)c->d_census.p;
+    HIP_TRY(hipMemsetAsync(dcounts, 0, 64 * 3 * sizeof(uint64_t), st));
+    if (n <= CENSUS_LANE_MAX_N) {
+        CensusArgs a;
+        a.n = n;
+        a.gen = generator;
+        a.key = key;
+        a.first = first;
+        a.count = count;
+        a.counts = dcounts;
+        const uint64_t want = (count + 255) / 256;
+        const int blocks = (int)std::min<uint64_t>(want, (uint64_t)c->cus * 8);
+        HIP_TRY(launch_census_lanes(a, blocks, st));
+    } else {
+        // generate chunks into device memory and walk them as a batch; the
+        // histogram row 3n..3n+2 accumulates the results
+        const uint32_t chunk = 1u << 16;
+        const uint64_t nn = (uint64_t)n * n;
+        HIP_TRY(c->d_gen.reserve((size_t)chunk * (nn + sizeof(int64_t) + sizeof(int32_t) + 1) + 64));
+        uint8_t *mats = (uint8_t *)c->d_gen.p;
+        int64_t *offs = (int64_t *)(mats + (((size_t)chunk * nn + 15) / 16) * 16);
+        int32_t *ns = (int32_t *)(offs + chunk);
+        uint8_t *out = (uint8_t *)(ns + chunk);
+        if ((rc = c->reserve_work((int32_t)chunk, (int64_t)chunk * n))) return rc;
+        for (uint64_t done = 0; done < count; done += chunk) {
+            const uint32_t cnt = (uint32_t)std::min<uint64_t>(chunk, count - done);
+            GenArgs ga;
+            ga.n = n;
+            ga.gen = generator;
+            ga.key = key;
+            ga.first = first + done;
+            ga.count = cnt;
+            ga.mats = mats;
+            ga.offs = offs;
+            ga.ns = ns;
+            HIP_TRY(launch_generate(ga, st));
+            Launch L;
+            memset(&L, 0, sizeof L);
+            L.pack_kind = 0;
+            L.mats_dev = mats;
+            L.offs_dev = offs;
+            L.ns_dev = ns;
+            L.count = (int32_t)cnt;
+            L.out_dev = out;
+            L.hist_dev = (uint64_t *)dcounts;
+            if ((rc = c->enqueue(L, st, false))) return rc;
+        }
+    }
+    uint64_t h[64 * 3];
+    HIP_TRY(hipMemcpyAsync(h, dcounts, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int row = n <= CENSUS_LANE_MAX_N ? 0 : 3 * n;
+    counts[0] = h[row];
+    counts[1] = h[row + 1];
+    counts[2] = h[row + 2];
+    return c->mark(st);
+}
+
 int32_t perm_tuning_get(perm_tuning *t)
 {
     if (!t) return set_error(PERM_EINVAL, "null pointer");

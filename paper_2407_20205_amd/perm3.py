@@ -26,6 +26,8 @@ PERM_EDEVICE = -4
 PERM_EAGAIN = -5
 PERM_ESTATE = -6
 PERM_RESULT_INVALID = 0xFF
+PERM_GEN_ENUMERATE = 0
+PERM_GEN_SPLITMIX = 1
 PERM_POLICY_SRPT = 0
 PERM_POLICY_FIFO = 1
 
@@ -91,6 +93,7 @@ EXPORTS = [
     ("perm_mod3_batch_dev", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     ("perm_mod3_batch_packed", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     ("perm_mod3_pack", _i32, [_vp, _i32, _vp]),
+    ("perm_mod3_census", _i32, [_i32, _i32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _vp]),
     ("perm_server_create", _i32, [_vp, _vp]),
     ("perm_server_submit", _i32, [_vp, _vp, _i32, ctypes.c_uint64]),
     ("perm_server_poll", _i32, [_vp, _vp, _i32, _vp, ctypes.c_int64]),
@@ -176,6 +179,13 @@ def perm_mod3_pack(A) -> np.ndarray:
     planes = np.zeros(max(2 * n, 1), dtype=np.uint64)
     _check(lib().perm_mod3_pack(_ptr(A) if A.size else None, n, _ptr(planes)))
     return planes[:2 * n]
+
+
+def perm_mod3_census(n: int, generator: int, key: int, first: int, count: int) -> tuple[int, int, int]:
+    """How many of the generated matrices have perm mod 3 = 0, 1, 2 (see include/perm3.h)."""
+    c = (ctypes.c_uint64 * 3)()
+    _check(lib().perm_mod3_census(n, generator, key, first, count, ctypes.addressof(c)))
+    return int(c[0]), int(c[1]), int(c[2])
 
 
 # ---------------------------------------------------------------- device calls (torch tensors)
