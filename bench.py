@@ -262,6 +262,45 @@ def bench_pi50(P, W, shards=64, ckdir=None):
     return out
 
 
+# ------------------------------------------------------------------ Monte Carlo (Section 4, Table 4)
+
+def read_table4():
+    rows = []
+    with open(os.path.join(ROOT, "tests", "golden", "table4_montecarlo.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                n, z, lg = line.split()
+                rows.append((int(n), int(z), 10 ** int(lg)))
+    return rows
+
+
+def bench_montecarlo(P, scale, n_min=6, n_max=30):
+    """Table 4's study: for each n, uniform random matrices (SplitMix64 draws made on the
+    device) and the fraction with perm = 0, at `scale` times the paper's trial counts."""
+    import math
+    out = {"scale": scale, "rows": [], "paper": "Table 4: about one day on 128 processors at scale 1"}
+    total_s = 0.0
+    for n, z_paper, trials_paper in read_table4():
+        if n > n_max or n < n_min:
+            continue
+        trials = max(1000, int(trials_paper * scale))
+        t0 = time.perf_counter()
+        c = P.perm_mod3_census(n, P.PERM_GEN_SPLITMIX, 4_000_000 + n, 0, trials)
+        sec = time.perf_counter() - t0
+        total_s += sec
+        p_ours = c[0] / trials
+        p_paper = z_paper / trials_paper
+        se = math.sqrt(p_ours * (1 - p_ours) / trials + p_paper * (1 - p_paper) / trials_paper)
+        row = {"n": n, "trials": trials, "zeros": c[0], "ones": c[1], "minus_ones": c[2],
+               "p0": p_ours, "p0_paper": p_paper, "z_score": (p_ours - p_paper) / se if se else 0.0,
+               "seconds": sec, "terms_per_s": trials * ((1 << n) - 1) / sec}
+        out["rows"].append(row)
+        log(f"n={n}: {trials} trials, P(perm=0) {p_ours:.5f} vs Table 4 {p_paper:.5f} "
+            f"(z = {row['z_score']:+.2f}), {sec:.2f} s")
+    out["seconds"] = total_s
+    return out
+
+
 # ------------------------------------------------------------------ serving
 
 def expected_work(W):
@@ -370,7 +409,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["headline", "single20", "batch", "serve", "large", "pi50"], default=None)
+    ap.add_argument("--only", choices=["headline", "single20", "batch", "serve", "large", "pi50", "montecarlo"],
+                    default=None)
+    ap.add_argument("--mc-scale", type=float, default=0.01, help="fraction of Table 4's trial counts")
+    ap.add_argument("--mc-n", default="6-30", help="range of n for the Monte Carlo study, e.g. 6-17")
     ap.add_argument("--checkpoint-dir", default=None, help="checkpoint files of the sharded Pi_50 run")
     ap.add_argument("--serve-count", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=None)
@@ -436,6 +478,9 @@ def main():
         log(f"large: n=44 {lg['n44_s']:.3f} s ({lg['n44_terms_per_s']:.3e} terms/s), 64 sparse n=40 "
             f"{lg['sparse40_s']:.3f} s ({lg['sparse40_terms_per_s']:.3e} terms/s)")
         line["large"] = lg
+    if args.only == "montecarlo":
+        lo, hi = (int(x) for x in args.mc_n.split("-"))
+        line["montecarlo"] = bench_montecarlo(P, args.mc_scale, lo, hi)
     if args.only == "pi50":
         line["pi50"] = bench_pi50(P, W, ckdir=args.checkpoint_dir)
     if args.only is None and not args.no_cpu:

@@ -155,7 +155,7 @@ struct GenArgs {                    // write matrices first .. first+count-1 as 
     int32_t *ns;                    // [count]
 };
 
-constexpr int CENSUS_LANE_MAX_N = 14;   // one matrix per lane up to this n
+constexpr int CENSUS_LANE_MAX_N = 20;   // one matrix per lane up to this n
 
 hipError_t launch_census_lanes(const CensusArgs &a, int grid_blocks, hipStream_t st);
 hipError_t launch_generate(const GenArgs &a, hipStream_t st);
