@@ -218,7 +218,7 @@ typedef struct {
     int32_t waves_per_simd;   /* persistent waves per SIMD (1..16)                        */
     int32_t body_log;         /* log2 of the unrolled Gray steps per block, n > mid_max_n:
                                  4, 5 or 6                                                  */
-    int32_t chunk_log_max;    /* largest per-lane chunk, log2 Gray indices (8..30)        */
+    int32_t chunk_log_max;    /* largest per-lane chunk, log2 Gray indices (8..24)        */
     int32_t tasks_per_wave;   /* target tasks per persistent wave                         */
     int32_t direct_max_n;     /* n at or below which every step is tested exactly        */
     int32_t use_graphs;       /* 1: capture device-input calls into cached HIP graphs     */

@@ -19,12 +19,11 @@ struct MatMeta {
     int32_t n;
     int32_t m;          // log2 of the per-lane chunk length
     int32_t mode;       // WalkMode
-    uint32_t ntasks;    // 64 * S chunks per task
+    int32_t ul;         // log2 of the unrolled block (4, 5 or 6)
+    uint64_t ntasks;    // 64 * S chunks per task
     int64_t row_base;   // first RowW of this matrix
     uint64_t lo, hi;    // Gray index range [lo, hi)
     uint64_t c_first;   // first chunk index (lo >> m)
-    int32_t ul;         // log2 of the unrolled block (4, 5 or 6)
-    int32_t pad;
 };
 
 // counters[] slots
@@ -41,11 +40,11 @@ struct PlanArgs {
     int32_t waves_total, tasks_per_wave;
     MatMeta *meta;
     int32_t *order;               // [count] matrix index by decreasing n
-    uint32_t *task_start;         // [count + 1] first task of order[p]
+    uint64_t *task_start;         // [count + 1] first task of order[p]
     int64_t *tally;               // [count]
-    uint32_t *done;               // [count]
+    uint64_t *done;               // [count]
     uint8_t *status;              // [count] 0 ok, 1 invalid
-    uint32_t *counters;           // [CNT_COUNT]
+    uint64_t *counters;           // [CNT_COUNT]
     uint8_t *out;                 // [count]
     uint64_t *hist;               // [64 * 3] or null
 };
@@ -72,12 +71,12 @@ struct WalkArgs {
     const RowW *rows;
     const MatMeta *meta;
     const int32_t *order;
-    const uint32_t *task_start;
+    const uint64_t *task_start;
     int32_t count;
     int64_t *tally;
-    uint32_t *done;
+    uint64_t *done;
     const uint8_t *status;
-    uint32_t *counters;
+    uint64_t *counters;
     uint8_t *out;
     uint64_t *hist;
 };

@@ -219,7 +219,6 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
         mt.hi = 0;
         mt.c_first = 0;
         mt.ul = a.body_log;
-        mt.pad = 0;
         a.tally[k] = 0;
         a.done[k] = 0;
         a.status[k] = valid ? 0 : 1;
@@ -240,7 +239,9 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
             const bool fast_ok = n >= ul + 7 + slog && n > a.direct_max_n;
             int m;
             if (fast_ok) {
-                const int mmax = a.chunk_log_max < n - 6 - slog ? a.chunk_log_max : n - 6 - slog;
+                // a lane's int32 tally covers S chunks and a wave sums 64 lanes: S * 2^m <= 2^24
+                int mmax = a.chunk_log_max < n - 6 - slog ? a.chunk_log_max : n - 6 - slog;
+                if (mmax > 24 - slog) mmax = 24 - slog;
                 m = target_m;
                 if (m > mmax) m = mmax;
                 if (m < ul + 1) m = ul + 1;
@@ -257,7 +258,7 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
                 const uint64_t c1 = (hi - 1) >> m;
                 mt.c_first = c0;
                 const uint64_t per_task = 64ull << a.states_log;
-                mt.ntasks = (uint32_t)((c1 - c0 + per_task) / per_task);
+                mt.ntasks = (c1 - c0 + per_task) / per_task;
             } else {
                 mt.mode = MODE_NONE;
                 a.out[k] = finish_mod3(n, 0);
@@ -276,12 +277,12 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
         const uint64_t v = p < a.count ? (uint64_t)a.meta[a.order[p]].ntasks : 0;
         uint64_t tot;
         const uint64_t incl = block_incl_scan_1024<uint64_t>(v, s_u64, tot);
-        if (p < a.count) a.task_start[p] = (uint32_t)(running + incl - v);
+        if (p < a.count) a.task_start[p] = running + incl - v;
         running += tot;
     }
     if (tid == 0) {
-        a.task_start[a.count] = (uint32_t)running;
-        a.counters[CNT_TOTAL_TASKS] = (uint32_t)running;
+        a.task_start[a.count] = running;
+        a.counters[CNT_TOTAL_TASKS] = running;
     }
 
     // row offsets in matrix order
@@ -372,6 +373,13 @@ __device__ __forceinline__ uint32_t wave_index()
     return blockIdx.x * (WALK_BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
 }
 
+__device__ __forceinline__ uint64_t uniform64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 // Task scheduling shared by k_walk and k_tick: wave w first takes task w
 // with no atomic, then draws grid-size + counter; a wave whose first task is
 // past the end leaves at once, so small jobs touch the counter once per
@@ -383,14 +391,21 @@ __device__ __forceinline__ uint32_t next_task(uint32_t *queue, uint32_t nwaves, 
     return nwaves + __builtin_amdgcn_readfirstlane(t);
 }
 
+__device__ __forceinline__ uint64_t next_task64(uint64_t *queue, uint32_t nwaves, int lane)
+{
+    uint64_t t = 0;
+    if (lane == 0) t = atomicAdd((unsigned long long *)queue, 1ull);
+    return (uint64_t)nwaves + uniform64(t);
+}
+
 template <int S>
 __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
 {
     const int lane = threadIdx.x & 63;
-    const uint32_t total = a.counters[CNT_TOTAL_TASKS];
+    const uint64_t total = a.counters[CNT_TOTAL_TASKS];
     const uint32_t nwaves = gridDim.x * (WALK_BLOCK / 64);
-    const cptr<uint32_t> task_start = to_const(a.task_start);
-    for (uint32_t tau = wave_index(); tau < total; tau = next_task(&a.counters[CNT_QUEUE], nwaves, lane)) {
+    const cptr<uint64_t> task_start = to_const(a.task_start);
+    for (uint64_t tau = wave_index(); tau < total; tau = next_task64(&a.counters[CNT_QUEUE], nwaves, lane)) {
         // position p in the order whose tasks contain tau: the largest p with
         // task_start[p] <= tau (matrices without tasks share their successor's start)
         int lo = 0, hi = a.count;
@@ -400,12 +415,12 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
         }
         const int k = to_const(a.order)[lo];
         const MatMeta mt = load_const(a.meta, k);
-        const uint32_t q = tau - task_start[lo];
+        const uint64_t q = tau - task_start[lo];
 
         int tally = 0;
         if (to_const(a.status)[k] == 0) {
             const cptr<RowW> R = to_const(a.rows) + mt.row_base;
-            const uint64_t c = mt.c_first + (uint64_t)q * (64u * S) + (uint64_t)lane;
+            const uint64_t c = mt.c_first + q * (64u * S) + (uint64_t)lane;
             if (mt.ul == 4)
                 tally = walk_task<4, S>(R, mt, c);
             else if (mt.ul == 6)
@@ -418,7 +433,7 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
         if (lane == 0) {
             if (sum != 0) atomicAdd((unsigned long long *)&a.tally[k], (unsigned long long)(long long)sum);
             __threadfence();
-            const uint32_t prev = atomicAdd(&a.done[k], 1u);
+            const uint64_t prev = atomicAdd((unsigned long long *)&a.done[k], 1ull);
             if (prev + 1 == mt.ntasks) {
                 __threadfence();
                 const long long T = __hip_atomic_load((long long *)&a.tally[k], __ATOMIC_RELAXED,

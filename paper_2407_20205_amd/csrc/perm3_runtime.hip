@@ -77,7 +77,7 @@ perm_tuning default_tuning()
 bool tuning_valid(const perm_tuning &t)
 {
     return t.waves_per_simd >= 1 && t.waves_per_simd <= 16 && t.body_log >= 4 && t.body_log <= 6 &&
-           t.chunk_log_max >= 8 && t.chunk_log_max <= 30 && t.tasks_per_wave >= 1 &&
+           t.chunk_log_max >= 8 && t.chunk_log_max <= 24 && t.tasks_per_wave >= 1 &&
            t.tasks_per_wave <= 1024 && t.direct_max_n >= t.body_log + 6 && t.direct_max_n <= 63 &&
            (t.use_graphs == 0 || t.use_graphs == 1) &&
            (t.states_per_lane == 1 || t.states_per_lane == 2 || t.states_per_lane == 4) &&
@@ -96,7 +96,10 @@ hipError_t DevBuf::reserve(size_t n)
 {
     if (n <= cap) return hipSuccess;
     if (p) {
-        hipError_t e = hipFree(p);
+        // earlier asynchronous calls may still read the old buffer
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
+        e = hipFree(p);
         p = nullptr;
         cap = 0;
         if (e != hipSuccess) return e;
@@ -196,11 +199,11 @@ int32_t Context::reserve_work(int32_t count, int64_t rows)
     void *before[8] = {meta.p, order.p, task_start.p, tally.p, done.p, status.p, counters.p, rowbuf.p};
     HIP_TRY(meta.reserve(c * sizeof(MatMeta)));
     HIP_TRY(order.reserve(c * sizeof(int32_t)));
-    HIP_TRY(task_start.reserve((c + 1) * sizeof(uint32_t)));
+    HIP_TRY(task_start.reserve((c + 1) * sizeof(uint64_t)));
     HIP_TRY(tally.reserve(c * sizeof(int64_t)));
-    HIP_TRY(done.reserve(c * sizeof(uint32_t)));
+    HIP_TRY(done.reserve(c * sizeof(uint64_t)));
     HIP_TRY(status.reserve(c));
-    HIP_TRY(counters.reserve(CNT_COUNT * sizeof(uint32_t)));
+    HIP_TRY(counters.reserve(CNT_COUNT * sizeof(uint64_t)));
     HIP_TRY(rowbuf.reserve((size_t)std::max<int64_t>(rows, 1) * sizeof(RowW)));
     void *after[8] = {meta.p, order.p, task_start.p, tally.p, done.p, status.p, counters.p, rowbuf.p};
     if (memcmp(before, after, sizeof before) != 0) drop_graphs();
@@ -238,11 +241,11 @@ PlanArgs Context::plan_args(const int32_t *ns_dev, int32_t count, uint8_t *out_d
     a.tasks_per_wave = tuning.tasks_per_wave;
     a.meta = (MatMeta *)meta.p;
     a.order = (int32_t *)order.p;
-    a.task_start = (uint32_t *)task_start.p;
+    a.task_start = (uint64_t *)task_start.p;
     a.tally = (int64_t *)tally.p;
-    a.done = (uint32_t *)done.p;
+    a.done = (uint64_t *)done.p;
     a.status = (uint8_t *)status.p;
-    a.counters = (uint32_t *)counters.p;
+    a.counters = (uint64_t *)counters.p;
     a.out = out_dev;
     a.hist = hist_dev;
     return a;
@@ -254,12 +257,12 @@ WalkArgs Context::walk_args(int32_t count, uint8_t *out_dev, uint64_t *hist_dev)
     w.rows = (const RowW *)rowbuf.p;
     w.meta = (const MatMeta *)meta.p;
     w.order = (const int32_t *)order.p;
-    w.task_start = (const uint32_t *)task_start.p;
+    w.task_start = (const uint64_t *)task_start.p;
     w.count = count;
     w.tally = (int64_t *)tally.p;
-    w.done = (uint32_t *)done.p;
+    w.done = (uint64_t *)done.p;
     w.status = (const uint8_t *)status.p;
-    w.counters = (uint32_t *)counters.p;
+    w.counters = (uint64_t *)counters.p;
     w.out = out_dev;
     w.hist = hist_dev;
     return w;
