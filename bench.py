@@ -356,15 +356,18 @@ def replay_fifo_baseline(P, tr):
     return lat, res, (time.monotonic_ns() - start) / 1e9
 
 
-def bench_serve(P, W, torch, rate, count, batched_terms_per_s):
+def bench_serve(P, W, torch, rate, count, batched_terms_per_s, quantum=1 << 33, baseline=True):
     ew = expected_work(W)
     if rate is None:
         rate = 0.7 * batched_terms_per_s / ew
     tr = W.serve_trace(count=count, rate=rate)
     terms = float(sum((1 << int(n)) - 1 for n in tr.ns))
     log(f"serve: {count} requests at {rate:.1f}/s, {terms:.3e} terms")
-    lat, res, span, st = replay_server(P, tr, P.PERM_POLICY_SRPT, 1 << 33)
-    log(f"serve: continuous batching done in {span:.2f} s")
+    lat, res, span, st = replay_server(P, tr, P.PERM_POLICY_SRPT, quantum)
+    log(f"serve: continuous batching done in {span:.2f} s, p50 {pct(lat, 50):.3f} ms, p99 {pct(lat, 99):.3f} ms")
+    if not baseline:
+        return {"rate_per_s": rate, "quantum": quantum, "requests_per_s": count / span, "p50_ms": pct(lat, 50),
+                "p99_ms": pct(lat, 99), "ticks": int(st.ticks)}
     blat, bres, bspan = replay_fifo_baseline(P, tr)
     log(f"serve: FIFO baseline done in {bspan:.2f} s")
     return {
@@ -375,6 +378,7 @@ def bench_serve(P, W, torch, rate, count, batched_terms_per_s):
         "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "mean_ms": float(np.mean(lat)),
         "terms_per_s": terms / span,
         "ticks": int(st.ticks),
+        "quantum": quantum,
         "baseline_fifo_one_launch_per_request": {"p50_ms": pct(blat, 50), "p99_ms": pct(blat, 99),
                                                  "requests_per_s": count / bspan},
         "results_identical_to_baseline": bool(res == bres),
@@ -416,6 +420,7 @@ def main():
     ap.add_argument("--checkpoint-dir", default=None, help="checkpoint files of the sharded Pi_50 run")
     ap.add_argument("--serve-count", type=int, default=20000)
     ap.add_argument("--serve-rate", type=float, default=None)
+    ap.add_argument("--serve-quantum-log", type=int, default=33, help="log2 of the Gray indices per tick")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true",
                     help="skip the one-launch-per-matrix and FIFO baselines (for profiling)")
@@ -472,7 +477,8 @@ def main():
         line["batch"] = bt
     if args.only in (None, "serve"):
         cap = line.get("batch", {}).get("terms_per_s") or 8e12
-        line["serve"] = bench_serve(P, W, torch, args.serve_rate, args.serve_count, cap)
+        line["serve"] = bench_serve(P, W, torch, args.serve_rate, args.serve_count, cap,
+                                    quantum=1 << args.serve_quantum_log, baseline=not args.no_baselines)
     if args.only in (None, "large"):
         lg = bench_large(P, W, torch)
         log(f"large: n=44 {lg['n44_s']:.3f} s ({lg['n44_terms_per_s']:.3e} terms/s), 64 sparse n=40 "
