@@ -109,7 +109,7 @@ def bench_headline(P, W, torch, steps, warmup):
             "traffic": measured_traffic(),
             "ops_per_term": OPS_PER_TERM,
             "terms_per_launch": terms,
-            "kernel": "k_walk<5,1>",
+            "kernel": "k_walk<1> (32-step blocks at n = 36)",
         },
         "paper_ops_frac": PAPER_OPS_PER_TERM_2W * terms / hot_s / PEAK_LANE_OPS,
     }
