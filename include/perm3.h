@@ -78,6 +78,26 @@ int32_t perm_mod3(const uint8_t *A, int32_t n, uint8_t *out);
 int32_t perm_mod3_range_tally(const uint8_t *A, int32_t n, uint64_t begin, uint64_t end,
                           int64_t *tally);
 
+/*
+ * perm_mod3_range_tally_wide: T over a range of Gray indices of a matrix of
+ * up to 128 columns, two 64-bit words per plane (Section 3 names this as the
+ * ambitious case past n = 64, where Gray indices outgrow 64 bits).
+ *   A:         host, n*n bytes in {0,1,2}, 1 <= n <= PERM_MAX_N_WIDE
+ *   begin_hi, begin_lo:  the first Gray index, begin = begin_hi * 2^64 + begin_lo
+ *   count:     number of indices, 0 <= count <= PERM_WIDE_MAX_COUNT; the
+ *              range [begin, begin + count) must lie inside [0, 2^n]
+ *   *tally:    host int64, T(begin, begin + count) as for perm_mod3_range_tally
+ * Synchronous.  For n <= 63 the value equals perm_mod3_range_tally's.  The
+ * whole sum for n >= 64 (2^64 indices and more) is out of reach of one
+ * device; the call is the unit a sharded run over many devices adds up.
+ * PERM_EINVAL for n or count out of range, a range outside [0, 2^n] or a null
+ * pointer; PERM_EDOMAIN for an entry > 2 (perm_last_error_index() = offset).
+ */
+#define PERM_MAX_N_WIDE 128
+#define PERM_WIDE_MAX_COUNT (1ull << 62)
+int32_t perm_mod3_range_tally_wide(const uint8_t *A, int32_t n, uint64_t begin_hi, uint64_t begin_lo,
+                                   uint64_t count, int64_t *tally);
+
 /* --------------------------------------------------------------------------
  * Many matrices in one persistent launch.
  *

@@ -12,7 +12,8 @@ Two independent definitions live here:
 * the C oracle (``perm3_oracle.c``) -- Ryser's identity, eq. (2), walked in
   reflected-binary Gray-code order with UNPACKED centred residues (Section 3
   with its cmod3 reduction), threaded over blocks of consecutive Gray indices
-  as in Section 3.1.  It returns exact partial tallies T(a, b) and perm mod 3.
+  as in Section 3.1.  It returns exact partial tallies T(a, b) and perm mod 3,
+  and, for matrices of up to 128 columns, tallies over 128-bit Gray indices.
 
 Inputs are n x n uint8 matrices with entries in {0, 1, 2}; 2 stands for -1.
 """
@@ -30,6 +31,7 @@ _SRC = os.path.join(_HERE, "perm3_oracle.c")
 _LIB = os.path.join(_HERE, "libperm3_oracle.so")
 
 MAX_N = 63
+MAX_N_WIDE = 128
 
 
 def build(force: bool = True) -> str:
@@ -70,6 +72,14 @@ def lib():
         L.oracle_census.restype = ctypes.c_int
         L.oracle_splitmix64.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
         L.oracle_splitmix64.restype = ctypes.c_uint64
+        L.oracle_term_wide.argtypes = [u8p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
+        L.oracle_term_wide.restype = ctypes.c_int
+        L.oracle_range_tally_wide.argtypes = [u8p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                              ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+        L.oracle_range_tally_wide.restype = ctypes.c_int64
+        L.oracle_range_tally_wide_mt.argtypes = [u8p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                                 ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.oracle_range_tally_wide_mt.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -140,6 +150,28 @@ def census(n: int, generator: int, key: int, first: int, count: int) -> tuple[in
 def splitmix64(key: int, q: int) -> int:
     """The q-th output (q >= 1) of SplitMix64 seeded with key."""
     return int(lib().oracle_splitmix64(key, q))
+
+
+def term_wide(A, i: int) -> int:
+    """One Ryser term by its definition at a Gray index of up to 128 bits (n <= 128)."""
+    A, n = _mat(A)
+    return lib().oracle_term_wide(_ptr(A), n, i >> 64, i & ((1 << 64) - 1))
+
+
+def range_tally_wide(A, begin: int, count: int, threads: int | None = None) -> int:
+    """Exact T(begin, begin + count) for n <= 128 with 128-bit Gray indices (count <= 2^62)."""
+    A, n = _mat(A)
+    ok = ctypes.c_int(0)
+    hi, lo = begin >> 64, begin & ((1 << 64) - 1)
+    if not 0 <= begin < (1 << 128) or not 0 <= count < (1 << 64):
+        raise ValueError("begin must fit 128 bits and count 64 bits")
+    if threads is None or threads <= 1:
+        v = lib().oracle_range_tally_wide(_ptr(A), n, hi, lo, count, ctypes.byref(ok))
+    else:
+        v = lib().oracle_range_tally_wide_mt(_ptr(A), n, hi, lo, count, threads, ctypes.byref(ok))
+    if not ok.value:
+        raise ValueError("invalid matrix or range")
+    return int(v)
 
 
 def signed(A) -> list[list[int]]:

@@ -275,3 +275,160 @@ int oracle_census(int n, int generator, uint64_t key, uint64_t first, uint64_t c
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Matrices of up to 128 columns, Gray indices of up to 128 bits.
+ *
+ * Section 3 stops at n <= 64, where a row and a Gray index each fit one
+ * 64-bit word, and notes that larger n would take a second word.  The sums
+ * are the same: T(a, b) over Gray indices a <= i < b with the state
+ * g(i) = i xor (i >> 1) now a 128-bit row set.  Only ranges are offered: the
+ * whole sum for n >= 64 has 2^64 terms or more.                           */
+
+#define ORACLE_MAX_N_WIDE 128
+#define ORACLE_WIDE_MAX_COUNT ((uint64_t)1 << 62)
+
+typedef unsigned __int128 oracle_u128;
+
+static int valid_input_wide(const uint8_t *A, int n)
+{
+    if (n < 1 || n > ORACLE_MAX_N_WIDE || A == NULL) return 0;
+    for (int k = 0; k < n * n; ++k)
+        if (A[k] > 2) return 0;
+    return 1;
+}
+
+static int popcount128(oracle_u128 x)
+{
+    return popcount64((uint64_t)x) + popcount64((uint64_t)(x >> 64));
+}
+
+static int trailing_zeros128(oracle_u128 x)
+{
+    int t = 0;
+    while (!(x & 1u)) { x >>= 1; ++t; }
+    return t;
+}
+
+/* [a, a + count) inside [0, 2^n], without forming 2^128. */
+static int range_fits_wide(int n, oracle_u128 a, uint64_t count)
+{
+    if (count > ORACLE_WIDE_MAX_COUNT) return 0;
+    if (n == 128) return count == 0 || a <= (oracle_u128)0 - (oracle_u128)count;
+    oracle_u128 total = (oracle_u128)1 << n;
+    return a <= total && (oracle_u128)count <= total - a;
+}
+
+/* One term by its definition at the 128-bit Gray index hi * 2^64 + lo. */
+int oracle_term_wide(const uint8_t *A, int n, uint64_t i_hi, uint64_t i_lo)
+{
+    if (!valid_input_wide(A, n)) return 0;
+    oracle_u128 i = ((oracle_u128)i_hi << 64) | i_lo;
+    oracle_u128 S = i ^ (i >> 1);
+    int prod = 1;
+    for (int col = 0; col < n; ++col) {
+        int64_t sum = 0;
+        for (int k = 0; k < n; ++k)
+            if ((S >> k) & 1u) sum += entry(A, n, k, col);
+        prod *= centred_mod3(sum);
+    }
+    return (popcount128(S) & 1) ? -prod : prod;
+}
+
+/* T over [a, a + count), a = a_hi * 2^64 + a_lo: the Gray walk of
+ * oracle_range_tally on 128-bit indices.  *ok = 0 on invalid input. */
+int64_t oracle_range_tally_wide(const uint8_t *A, int n, uint64_t a_hi, uint64_t a_lo, uint64_t count,
+                                int *ok)
+{
+    if (ok) *ok = 0;
+    if (!valid_input_wide(A, n)) return 0;
+    oracle_u128 a = ((oracle_u128)a_hi << 64) | a_lo;
+    if (!range_fits_wide(n, a, count)) return 0;
+    if (ok) *ok = 1;
+    if (count == 0) return 0;
+
+    int E[ORACLE_MAX_N_WIDE][ORACLE_MAX_N_WIDE];   /* 64 KB of stack */
+    for (int k = 0; k < n; ++k)
+        for (int col = 0; col < n; ++col)
+            E[k][col] = entry(A, n, k, col);
+
+    int v[ORACLE_MAX_N_WIDE];
+    oracle_u128 state = a ^ (a >> 1);
+    for (int col = 0; col < n; ++col) {
+        int64_t sum = 0;
+        for (int k = 0; k < n; ++k)
+            if ((state >> k) & 1u) sum += E[k][col];
+        v[col] = centred_mod3(sum);
+    }
+
+    int64_t s = 0;
+    for (uint64_t step = 0; step < count; ++step) {
+        oracle_u128 i = a + step;
+        if (step > 0) {
+            int t = trailing_zeros128(i);
+            int out = (int)((state >> t) & 1u);     /* row t leaves the subset */
+            state ^= (oracle_u128)1 << t;
+            for (int col = 0; col < n; ++col)
+                v[col] = centred_mod3(out ? v[col] - E[t][col] : v[col] + E[t][col]);
+        }
+        int prod = 1;
+        for (int col = 0; col < n; ++col) prod *= v[col];
+        s += (popcount128(state) & 1) ? -prod : prod;
+    }
+    return s;
+}
+
+typedef struct {
+    const uint8_t *A;
+    int n;
+    oracle_u128 a;
+    uint64_t count;
+    int64_t out;
+    int ok;
+} oracle_wide_job;
+
+static void *oracle_wide_job_run(void *p)
+{
+    oracle_wide_job *j = (oracle_wide_job *)p;
+    j->out = oracle_range_tally_wide(j->A, j->n, (uint64_t)(j->a >> 64), (uint64_t)j->a, j->count, &j->ok);
+    return NULL;
+}
+
+/* The same split over host threads into consecutive blocks (Section 3.1). */
+int64_t oracle_range_tally_wide_mt(const uint8_t *A, int n, uint64_t a_hi, uint64_t a_lo, uint64_t count,
+                                   int nthreads, int *ok)
+{
+    if (ok) *ok = 0;
+    if (!valid_input_wide(A, n)) return 0;
+    oracle_u128 a = ((oracle_u128)a_hi << 64) | a_lo;
+    if (!range_fits_wide(n, a, count)) return 0;
+    if (nthreads < 1) nthreads = 1;
+    if (nthreads > 256) nthreads = 256;
+    if (count < (uint64_t)nthreads * 4096u) nthreads = 1;
+
+    oracle_wide_job jobs[256];
+    pthread_t th[256];
+    for (int k = 0; k < nthreads; ++k) {
+        uint64_t b0 = (uint64_t)((oracle_u128)count * (uint64_t)k / (uint64_t)nthreads);
+        uint64_t b1 = (uint64_t)((oracle_u128)count * (uint64_t)(k + 1) / (uint64_t)nthreads);
+        jobs[k].A = A; jobs[k].n = n;
+        jobs[k].a = a + b0;
+        jobs[k].count = b1 - b0;
+        jobs[k].out = 0; jobs[k].ok = 0;
+    }
+    int started = 0;
+    for (int k = 1; k < nthreads; ++k) {
+        if (pthread_create(&th[k], NULL, oracle_wide_job_run, &jobs[k]) != 0) break;
+        started = k;
+    }
+    oracle_wide_job_run(&jobs[0]);
+    for (int k = started + 1; k < nthreads; ++k)
+        oracle_wide_job_run(&jobs[k]);
+    for (int k = 1; k <= started; ++k) pthread_join(th[k], NULL);
+
+    int64_t s = 0;
+    int all_ok = 1;
+    for (int k = 0; k < nthreads; ++k) { s += jobs[k].out; all_ok &= jobs[k].ok; }
+    if (ok) *ok = all_ok;
+    return s;
+}

@@ -127,6 +127,28 @@ hipError_t launch_bipedal_ops(const uint32_t *in, int count, uint32_t *out, hipS
 
 constexpr int WALK_BLOCK = 256;   // 4 waves, one per SIMD
 
+// Matrices of up to 128 columns: one Gray range of one matrix with 128-bit
+// indices.  The range [B + off_lo, B + off_hi) is held relative to the
+// chunk-aligned base B = c0 * 2^m, so every offset fits in 64 bits even when
+// the range ends at 2^128.
+struct RowX;
+
+struct WideArgs {
+    const RowX *rows;             // [n]
+    int32_t n, m, mode, ul;       // chunk log m, WalkMode, block log
+    uint64_t c0_lo, c0_hi;        // first chunk index c0 (128-bit)
+    uint64_t off_lo, off_hi;      // the range, relative to B
+    uint64_t ntasks;              // 64 chunks per task
+    uint64_t *queue;              // task counter, cleared by the pack kernel
+    int64_t *tally;               // the range's T, cleared by the pack kernel
+};
+
+constexpr int WIDE_MAX_N = 128;
+
+hipError_t launch_pack_wide(const uint8_t *A, int n, RowX *rows, uint64_t *queue, int64_t *tally,
+                            hipStream_t st);
+hipError_t launch_walk_wide(const WideArgs &a, int grid_blocks, hipStream_t st);
+
 }  // namespace perm3
 
 namespace perm3 {

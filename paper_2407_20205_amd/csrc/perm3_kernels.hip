@@ -15,37 +15,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "perm3_device.hpp"
 #include "perm3_internal.h"
 #include "perm3_walk.hpp"
 
 namespace perm3 {
 
 // ------------------------------------------------------------------ helpers
-
-// Read-only data seen through the constant address space: wave-uniform loads
-// from it become scalar loads into SGPRs.
-#define PERM3_CONST __attribute__((address_space(4)))
-template <typename T>
-using cptr = const PERM3_CONST T *;
-
-template <typename T>
-__device__ __forceinline__ cptr<T> to_const(const T *p)
-{
-    return reinterpret_cast<cptr<T>>(reinterpret_cast<uintptr_t>(p));
-}
-
-// p[i] copied out word by word (wave-uniform i: scalar loads).
-template <typename T>
-__device__ __forceinline__ T load_const(const T *p, int64_t i)
-{
-    static_assert(sizeof(T) % 4 == 0, "word-sized records");
-    const cptr<uint32_t> w = reinterpret_cast<cptr<uint32_t>>(reinterpret_cast<uintptr_t>(p + i));
-    T v;
-    uint32_t *d = reinterpret_cast<uint32_t *>(&v);
-#pragma unroll
-    for (size_t k = 0; k < sizeof(T) / 4; ++k) d[k] = w[k];
-    return v;
-}
 
 __device__ __forceinline__ Masks masks_for(int n)
 {
@@ -54,39 +30,6 @@ __device__ __forceinline__ Masks masks_for(int n)
     mk.lo = (uint32_t)full;
     mk.hi = (uint32_t)(full >> 32);
     return mk;
-}
-
-// Sum over the 64 lanes of a wavefront: an inclusive scan inside each row of
-// 16 lanes with DPP row shifts, then the four row totals read as scalars.
-// Every lane must be active.
-__device__ __forceinline__ int wave_sum(int v)
-{
-    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);   // row_shr:1
-    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);   // row_shr:2
-    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);   // row_shr:4
-    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);   // row_shr:8
-    return __builtin_amdgcn_readlane(v, 15) + __builtin_amdgcn_readlane(v, 31) +
-           __builtin_amdgcn_readlane(v, 47) + __builtin_amdgcn_readlane(v, 63);
-}
-
-// r = ((-1)^n * T) mod 3 in {0, 1, 2} (2 stands for -1).
-__device__ __forceinline__ uint8_t finish_mod3(int n, long long T)
-{
-    long long p = (n & 1) ? -T : T;
-    long long r = p % 3;
-    if (r < 0) r += 3;
-    return (uint8_t)r;
-}
-
-template <int UL>
-__device__ __forceinline__ void load_static_rows(cptr<RowW> R, StaticRows<UL> &sr)
-{
-#pragma unroll
-    for (int t = 0; t < UL; ++t) {
-        sr.m[t] = R[t].m_lo;
-        sr.s[t] = R[t].s_lo;
-        sr.sn[t] = R[t].sn_lo;
-    }
 }
 
 // Walk one lane's chunk c (chunk length 2^m) clipped to [lo, hi).
@@ -225,9 +168,15 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
         if (!valid) {
             a.out[k] = 0xFF;
         } else if (n == 0) {
-            // the empty product: perm of the 0 x 0 matrix is 1
-            a.out[k] = 1;
-            if (a.hist) atomicAdd((unsigned long long *)&a.hist[1], 1ull);
+            // the one subset (Gray index 0) is empty: its empty product makes
+            // a term of +1, and perm of the 0 x 0 matrix is 1
+            uint64_t lo, hi;
+            range_of(a, 0, lo, hi);
+            const long long T = lo < hi ? 1 : 0;
+            a.tally[k] = T;
+            const uint8_t r = finish_mod3(0, T);
+            a.out[k] = r;
+            if (a.hist) atomicAdd((unsigned long long *)&a.hist[r], 1ull);
         } else {
             uint64_t lo, hi;
             range_of(a, n, lo, hi);
@@ -365,37 +314,6 @@ __device__ __forceinline__ int walk_task(cptr<RowW> R, const MatMeta &mt, uint64
     StaticRows<UL> sr;
     if (mt.mode == MODE_FAST) load_static_rows<UL>(R, sr);
     return walk_lane_states<UL, S>(R, mt.n, mt.m, mt.mode, c, mt.lo, mt.hi, sr);
-}
-
-// The index of this wavefront in the grid (wave-uniform).
-__device__ __forceinline__ uint32_t wave_index()
-{
-    return blockIdx.x * (WALK_BLOCK / 64) + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-}
-
-__device__ __forceinline__ uint64_t uniform64(uint64_t v)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Task scheduling shared by k_walk and k_tick: wave w first takes task w
-// with no atomic, then draws grid-size + counter; a wave whose first task is
-// past the end leaves at once, so small jobs touch the counter once per
-// active wave instead of once per launched wave.
-__device__ __forceinline__ uint32_t next_task(uint32_t *queue, uint32_t nwaves, int lane)
-{
-    uint32_t t = 0;
-    if (lane == 0) t = atomicAdd(queue, 1u);
-    return nwaves + __builtin_amdgcn_readfirstlane(t);
-}
-
-__device__ __forceinline__ uint64_t next_task64(uint64_t *queue, uint32_t nwaves, int lane)
-{
-    uint64_t t = 0;
-    if (lane == 0) t = atomicAdd((unsigned long long *)queue, 1ull);
-    return (uint64_t)nwaves + uniform64(t);
 }
 
 template <int S>

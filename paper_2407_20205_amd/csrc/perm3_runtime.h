@@ -66,8 +66,8 @@ struct Context {
     std::mutex mu;
 
     DevBuf meta, order, task_start, tally, done, status, counters, rowbuf;
-    DevBuf d_stage, d_out, d_census, d_gen;
-    HostBuf h_stage;
+    DevBuf d_stage, d_out, d_census, d_gen, d_wide;
+    HostBuf h_stage, h_wide;
 
     std::map<GraphKey, hipGraphExec_t> graphs;
     hipEvent_t ev_walk0 = nullptr, ev_walk1 = nullptr, ev_all0 = nullptr, ev_all1 = nullptr;
@@ -95,5 +95,6 @@ struct Context {
 };
 
 int32_t get_context(Context **out);
+bool timing_enabled();   // perm_timing_enable() state of the calling thread
 
 }  // namespace perm3

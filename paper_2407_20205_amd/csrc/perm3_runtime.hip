@@ -119,6 +119,9 @@ hipError_t HostBuf::reserve(size_t n)
 {
     if (n <= cap) return hipSuccess;
     if (p) {
+        // a copy from the old buffer may still be queued after a failed call
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return e;
         (void)hipHostFree(p);
         p = nullptr;
         cap = 0;
@@ -182,6 +185,8 @@ int32_t get_context(Context **out)
     g_ctx[dev] = std::move(c);
     return PERM_OK;
 }
+
+bool timing_enabled() { return tl_timing; }
 
 int Context::waves_total() const { return cus * 4 * tuning.waves_per_simd; }
 int Context::grid_blocks() const { return cus * tuning.waves_per_simd; }

@@ -6,7 +6,10 @@
 //     { m_lo, s_lo, sn_lo, -, m_hi, s_hi, sn_hi, - }
 // where sn = s xor m is the sgn word of the NEGATED row: subtracting a row is
 // adding its negation, and negating a bipedal vector flips sgn exactly where
-// mag is set (every zero, (0,0) or (0,1), stays a zero).
+// mag is set (every zero, (0,0) or (0,1), stays a zero).  Matrices of up to
+// 128 columns (two 64-bit words per plane, the widest case Section 3 names)
+// use RowX and 128-bit Gray indices; the walk itself only ever carries the
+// low word, so its cost per index does not grow with the width.
 //
 // Gray order (Section 3, RBC footnote): index i has subset g(i) = i ^ (i >> 1);
 // the step into i flips row t = ctz(i), which leaves the subset (subtract)
@@ -31,6 +34,16 @@ struct RowW {
     uint32_t m_lo, s_lo, sn_lo, pad0;
     uint32_t m_hi, s_hi, sn_hi, pad1;
 };
+
+// A row of a matrix with up to 128 columns: the walk's low word as in RowW,
+// then the mag and sgn words of columns 32 .. 127.
+struct RowX {
+    uint32_t m_lo, s_lo, sn_lo, pad0;
+    uint32_t m_w[3], pad1;
+    uint32_t s_w[3], pad2;
+};
+
+typedef unsigned __int128 u128;
 
 // Truth-table immediates for v_bitop3_b32(A, B, C): bit (4A + 2B + C) of the
 // immediate is the output, so A = 0xF0, B = 0xCC, C = 0xAA as bit patterns.
@@ -64,6 +77,12 @@ struct Masks {
     uint32_t lo, hi;   // all-ones over the n columns, split into words
 };
 
+struct MasksX {
+    uint32_t lo;       // columns 0 .. 31
+    uint32_t w[3];     // columns 32 .. 127, word by word
+    int nw;            // how many of w[] the matrix uses
+};
+
 // The Ryser term of Gray index i whose subset sum has low words (ml, sl):
 // zero unless every column sum is non-zero.  The high words are not carried
 // by the fast walk; when the low words pass, they are formed here from
@@ -83,12 +102,39 @@ PERM3_FN int exact_term(RP R, int n, uint64_t i, uint32_t ml, uint32_t sl, Masks
     return par ? -1 : 1;
 }
 
+// The same for a matrix of up to 128 columns and a 128-bit Gray index: the
+// words beyond the low one are formed from scratch one at a time, each tested
+// before the next is built, from the rows of g(i) (visited by their set bits).
+template <typename RP>
+PERM3_FN int exact_term(RP R, int n, u128 i, uint32_t ml, uint32_t sl, const MasksX &mk)
+{
+    if (ml != mk.lo) return 0;
+    const u128 g = i ^ (i >> 1);
+    const uint64_t g0 = (uint64_t)g, g1 = (uint64_t)(g >> 64);
+    int par = __builtin_popcount(sl & mk.lo) + (int)((uint32_t)i & 1u);
+    for (int w = 0; w < mk.nw; ++w) {
+        uint32_t mw = 0, sw = 0;
+        for (uint64_t x = g0; x; x &= x - 1) {
+            const int k = __builtin_ctzll(x);
+            bip_add(mw, sw, R[k].m_w[w], R[k].s_w[w]);
+        }
+        for (uint64_t x = g1; x; x &= x - 1) {
+            const int k = 64 + __builtin_ctzll(x);
+            bip_add(mw, sw, R[k].m_w[w], R[k].s_w[w]);
+        }
+        if (mw != mk.w[w]) return 0;
+        par += __builtin_popcount(sw & mk.w[w]);
+    }
+    (void)n;
+    return (par & 1) ? -1 : 1;
+}
+
 // Low words of the subset sum of g(i0): jump straight to a Gray state
 // (Section 3.1).  O(n) word operations per lane.
-template <typename RP>
-PERM3_FN void seed_lo(RP R, int n, uint64_t i0, uint32_t &ml, uint32_t &sl)
+template <typename RP, typename I>
+PERM3_FN void seed_lo(RP R, int n, I i0, uint32_t &ml, uint32_t &sl)
 {
-    const uint64_t g = i0 ^ (i0 >> 1);
+    const I g = i0 ^ (i0 >> 1);
     ml = 0;
     sl = 0;
     for (int k = 0; k < n; ++k) {
@@ -102,6 +148,17 @@ template <int UL>
 struct StaticRows {
     uint32_t m[UL], s[UL], sn[UL];
 };
+
+template <int UL, typename RP>
+PERM3_FN void load_static_rows(RP R, StaticRows<UL> &sr)
+{
+#pragma unroll
+    for (int t = 0; t < UL; ++t) {
+        sr.m[t] = R[t].m_lo;
+        sr.s[t] = R[t].s_lo;
+        sr.sn[t] = R[t].sn_lo;
+    }
+}
 
 // A wave-uniform word moved into a vector register.  bitop3 with a scalar
 // operand issues more slowly than with three vector operands on gfx950, so
@@ -119,13 +176,19 @@ PERM3_FN uint32_t to_vgpr(uint32_t x)
 // Exact re-walk of Gray indices ia+1 .. ib (ia itself already counted) for
 // the lanes whose block held a candidate, from the low words (ml, sl) of the
 // subset sum at ia; the high words are formed only where the low words pass.
-template <typename RP>
-PERM3_FN int rewalk_exact(RP R, int n, uint64_t ia, uint64_t ib, uint32_t ml, uint32_t sl, Masks mk)
+// Indices ia+1 .. ib lie in one aligned chunk above its first index, so the
+// flipped row and its direction come from the low 64 bits of i.  The loop
+// stops on reaching ib rather than on i > ib: ib may be the largest index
+// the type holds (the last index below 2^128).
+template <typename RP, typename I, typename MK>
+PERM3_FN int rewalk_exact(RP R, int n, I ia, I ib, uint32_t ml, uint32_t sl, const MK &mk)
 {
     int tally = 0;
-    for (uint64_t i = ia + 1; i <= ib; ++i) {
-        const int t = __builtin_ctzll(i);
-        const bool leave = (i >> (t + 1)) & 1u;
+    for (I i = ia; i != ib;) {
+        ++i;
+        const uint64_t il = (uint64_t)i;
+        const int t = __builtin_ctzll(il);
+        const bool leave = (il >> (t + 1)) & 1u;
         bip_add(ml, sl, R[t].m_lo, leave ? R[t].sn_lo : R[t].s_lo);
         tally += exact_term(R, n, i, ml, sl, mk);
     }
@@ -153,8 +216,11 @@ PERM3_FN int rewalk_exact(RP R, int n, uint64_t ia, uint64_t ib, uint32_t ml, ui
 // when some index in it has all its low columns non-zero (one 3-input max
 // per two states, or per two steps when S = 1).  Only then is the block
 // walked again exactly (rewalk_exact from the state saved at its first index).
-template <int UL, int S, typename RP>
-PERM3_FN int walk_chunks_fast(RP R, int n, int m, uint64_t c, Masks mk, const StaticRows<UL> &sr)
+//
+// The chunk index c is a uint64_t for n <= 63 and a u128 for wider matrices
+// (with MasksX); only the seed and the exact terms see its high bits.
+template <int UL, int S, typename RP, typename I, typename MK>
+PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const StaticRows<UL> &sr)
 {
     static_assert(S == 1 || S == 2 || S == 4, "1, 2 or 4 states per lane");
     constexpr uint32_t U = 1u << UL;
@@ -162,7 +228,7 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, uint64_t c, Masks mk, const St
     int tally = 0;
 #pragma unroll
     for (int q = 0; q < S; ++q) {
-        const uint64_t i0 = (c + 64u * (uint64_t)q) << m;
+        const I i0 = (c + (I)(64u * q)) << m;
         seed_lo(R, n, i0, ml[q], sl[q]);
         tally += exact_term(R, n, i0, ml[q], sl[q], mk);
     }
@@ -223,7 +289,7 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, uint64_t c, Masks mk, const St
                 const uint32_t last = b * U + U - (inner ? 0u : 1u);
 #pragma unroll
                 for (int q = 0; q < S; ++q) {
-                    const uint64_t i0 = (c + 64u * (uint64_t)q) << m;
+                    const I i0 = (c + (I)(64u * q)) << m;
                     tally += rewalk_exact(R, n, i0 + b * U, i0 + last, m0[q], s0[q], mk);
                 }
             }
@@ -235,11 +301,47 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, uint64_t c, Masks mk, const St
 #pragma unroll
             for (int q = 0; q < S; ++q) {
                 bip_add(ml[q], sl[q], rm, rs);
-                tally += exact_term(R, n, ((c + 64u * (uint64_t)q) << m) + ((uint64_t)half << UL), ml[q], sl[q], mk);
+                tally += exact_term(R, n, ((c + (I)(64u * q)) << m) + (I)((uint64_t)half << UL), ml[q], sl[q], mk);
             }
         }
     }
     return tally;
+}
+
+// All-ones over the n columns of a matrix with up to 128 columns, word by word.
+PERM3_FN MasksX masks_wide(int n)
+{
+    MasksX mk;
+    mk.lo = n >= 32 ? 0xffffffffu : ((1u << n) - 1u);
+    mk.nw = (n + 31) / 32 - 1;
+    for (int w = 0; w < 3; ++w) {
+        const int cols = n - 32 * (w + 1);
+        mk.w[w] = cols >= 32 ? 0xffffffffu : (cols <= 0 ? 0u : ((1u << cols) - 1u));
+    }
+    return mk;
+}
+
+// One lane's chunk of a range of 128-bit Gray indices.  Chunk cr (counted
+// from c0) covers [B + cr 2^m, B + (cr+1) 2^m) with B = c0 2^m, and the range
+// is [B + off_lo, B + off_hi); offsets stay below 2^64, so a range may end at
+// 2^128.  A whole chunk of a fast-mode matrix takes the unrolled walk; a
+// ragged end (or a small matrix) is seeded at its first index and tests every
+// index on the low word, forming the other words only where it passes.
+template <int UL, typename RP>
+PERM3_FN int walk_lane_wide(RP R, int n, int m, bool fast, u128 c0, uint64_t off_lo, uint64_t off_hi,
+                            uint64_t cr, const MasksX &mk, const StaticRows<UL> &sr)
+{
+    const uint64_t oa0 = cr << m;
+    const uint64_t oe0 = oa0 + (1ull << m);
+    const uint64_t oa = oa0 > off_lo ? oa0 : off_lo;
+    const uint64_t oe = oe0 < off_hi ? oe0 : off_hi;
+    if (oa >= oe) return 0;
+    if (fast && oa == oa0 && oe == oe0) return walk_chunks_fast<UL, 1>(R, n, m, c0 + cr, mk, sr);
+    const u128 base = c0 << m;
+    const u128 ia = base + oa;
+    uint32_t ml, sl;
+    seed_lo(R, n, ia, ml, sl);
+    return exact_term(R, n, ia, ml, sl, mk) + rewalk_exact(R, n, ia, base + (oe - 1), ml, sl, mk);
 }
 
 // Exact walk of an arbitrary range [a, e) with both words carried and every

@@ -17,6 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libperm3.so")
 
 PERM_MAX_N = 63
+PERM_MAX_N_WIDE = 128
+PERM_WIDE_MAX_COUNT = 1 << 62
 PERM_MAX_BATCH = 1 << 22
 PERM_OK = 0
 PERM_EINVAL = -1
@@ -89,6 +91,7 @@ _i32 = ctypes.c_int32
 EXPORTS = [
     ("perm_mod3", _i32, [_vp, _i32, _vp]),
     ("perm_mod3_range_tally", _i32, [_vp, _i32, ctypes.c_uint64, ctypes.c_uint64, _vp]),
+    ("perm_mod3_range_tally_wide", _i32, [_vp, _i32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _vp]),
     ("perm_mod3_batch", _i32, [_vp, _vp, _i32, _vp]),
     ("perm_mod3_batch_dev", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     ("perm_mod3_batch_packed", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
@@ -161,6 +164,17 @@ def perm_mod3_range_tally(A, begin: int, end: int) -> int:
     A, n = _mat(A)
     t = ctypes.c_int64(0)
     _check(lib().perm_mod3_range_tally(_ptr(A) if A.size else None, n, begin, end, ctypes.addressof(t)))
+    return int(t.value)
+
+
+def perm_mod3_range_tally_wide(A, begin: int, count: int) -> int:
+    """T(begin, begin + count) for an n x n matrix with n <= 128 (Gray indices up to 2^128)."""
+    A, n = _mat(A)
+    if not 0 <= begin < (1 << 128) or not 0 <= count < (1 << 64):
+        raise ValueError("begin must fit 128 bits and count 64 bits")
+    t = ctypes.c_int64(0)
+    _check(lib().perm_mod3_range_tally_wide(_ptr(A) if A.size else None, n, begin >> 64,
+                                            begin & ((1 << 64) - 1), count, ctypes.addressof(t)))
     return int(t.value)
 
 

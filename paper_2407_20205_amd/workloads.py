@@ -187,6 +187,59 @@ def hidden_block_diagonal(sizes, seed: int) -> tuple[np.ndarray, list]:
 
 # ---- the digits-of-pi matrix of Section 3.1 ---------------------------------
 
+def wide_block(n1: int, n2: int, seed: int, pairs: int = 3, shuffle: bool = True, M=None):
+    """A = M (+) D for matrices of up to 128 columns: M (n1 x n1, uniform unless given) in the
+    first n1 rows and columns, D (n2 x n2) in the last n2.  Column c of D holds one +-1 in row
+    p(c) (p a random permutation) and `pairs` further pairs of opposite entries (1 and 2, i.e. 1
+    and -1) in other rows, so the entries of every D column over all n2 rows add up to that one
+    +-1.  With `shuffle` the n columns of A are permuted at random (rows keep their order).
+    Returns (A, M, D)."""
+    g = rng(seed)
+    n = n1 + n2
+    M = g.integers(0, 3, size=(n1, n1), dtype=np.uint8) if M is None else np.asarray(M, dtype=np.uint8)
+    assert M.shape == (n1, n1)
+    D = np.zeros((n2, n2), dtype=np.uint8)
+    piv = g.permutation(n2)
+    for c in range(n2):
+        D[piv[c], c] = g.integers(1, 3)
+        others = [r for r in range(n2) if r != piv[c]]
+        k = min(pairs, len(others) // 2)
+        if k:
+            rows = g.choice(others, size=2 * k, replace=False)
+            for t in range(k):
+                v = int(g.integers(1, 3))
+                D[rows[2 * t], c] = v
+                D[rows[2 * t + 1], c] = 3 - v
+    A = np.zeros((n, n), dtype=np.uint8)
+    A[:n1, :n1] = M
+    A[n1:, n1:] = D
+    if shuffle:
+        A = A[:, g.permutation(n)]
+    return np.ascontiguousarray(A), M, D
+
+
+SEED_WIDE = 6
+
+
+def wide_128():
+    """The 128-column workload: M (+) D with M a hidden triangular 36 x 36 matrix (so perm(M) is
+    the product of its diagonal) and D 92 x 92, columns shuffled.  Returns (A, M, d, D) with d
+    the diagonal behind M."""
+    M, d = hidden_triangular(36, SEED_WIDE)
+    A, M, D = wide_block(36, 92, SEED_WIDE, pairs=3, shuffle=True, M=M)
+    return A, M, d, D
+
+
+def rank_one_signs(n: int, seed: int) -> np.ndarray:
+    """a_kj = e_k * f_j with random signs e, f: every entry is +-1 (bytes 1 and 2) and all columns
+    of a row subset have the same sum up to sign, so about two thirds of all Ryser terms are
+    non-zero at any n."""
+    g = rng(seed)
+    e = g.integers(0, 2, size=n)
+    f = g.integers(0, 2, size=n)
+    return np.where(e[:, None] == f[None, :], 1, 2).astype(np.uint8)
+
+
 def _arctan_inv(x: int, unity: int) -> int:
     """arctan(1/x) * unity by its alternating power series, in integers."""
     total = term = unity // x

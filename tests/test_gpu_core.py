@@ -82,6 +82,15 @@ def test_small_vs_brute_force(n):
         assert P.perm_mod3(A) == want, (n, s)
 
 
+def test_empty_matrix_range_tally():
+    # the 0 x 0 matrix has one subset, the empty one, whose term is +1
+    Z = np.zeros((0, 0), np.uint8)
+    for a, b in [(0, 1), (0, 0), (1, 1)]:
+        want = oracle.range_tally(Z, a, b)
+        assert want == (1 if (a, b) == (0, 1) else 0)
+        assert P.perm_mod3_range_tally(Z, a, b) == want, (a, b)
+
+
 @pytest.mark.parametrize("n", [9, 11, 12, 13, 15, 16, 17, 18, 19, 20, 21, 22, 24, 25, 26])
 def test_random_vs_oracle(n):
     for s in range(3):

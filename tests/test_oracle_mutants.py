@@ -103,3 +103,80 @@ def test_mutant_is_caught(tmp_path, name):
     old, new = MUTANTS[name]
     L = _build(tmp_path, name, old, new)
     assert not pins_pass(L), f"planted mistake {name} slipped through the pins"
+
+
+# ---------------------------------------------------------------- 128-bit Gray indices
+
+WIDE_MUTANTS = {
+    "wide_state_low_half": ("oracle_u128 state = a ^ (a >> 1);",
+                            "oracle_u128 state = (uint64_t)(a ^ (a >> 1));"),
+    "wide_popcount_low_half": ("return popcount64((uint64_t)x) + popcount64((uint64_t)(x >> 64));",
+                               "return popcount64((uint64_t)x);"),
+    "wide_seed_drops_high_rows": ("if ((state >> k) & 1u) sum += E[k][col];",
+                                  "if (k < 64 && ((state >> k) & 1u)) sum += E[k][col];"),
+    "wide_step_ctz_low_word": ("int t = trailing_zeros128(i);",
+                               "int t = trailing_zeros64((uint64_t)i | ((uint64_t)1 << 63));"),
+    "wide_term_gray_low_half": ("oracle_u128 S = i ^ (i >> 1);",
+                                "oracle_u128 S = (uint64_t)i ^ ((uint64_t)i >> 1);"),
+    "wide_range_one_too_many": ("for (uint64_t step = 0; step < count; ++step) {",
+                                "for (uint64_t step = 0; step <= count; ++step) {"),
+}
+
+
+def _wide(L):
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    L.oracle_term_wide.argtypes = [u8p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64]
+    L.oracle_term_wide.restype = ctypes.c_int
+    L.oracle_range_tally_wide.argtypes = [u8p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
+                                          ctypes.c_uint64, ctypes.POINTER(ctypes.c_int)]
+    L.oracle_range_tally_wide.restype = ctypes.c_int64
+    return L
+
+
+def wide_pins_pass(L) -> bool:
+    """The pins of test_oracle_wide.py, on a mutated copy: narrow equality, per-term
+    definition on ranges across 2^63, 2^64 and at the top, and the block closed form."""
+    ok = ctypes.c_int(0)
+    M64 = (1 << 64) - 1
+
+    def tally(p, n, a, c):
+        return L.oracle_range_tally_wide(p, n, a >> 64, a & M64, c, ctypes.byref(ok))
+
+    def term(p, n, i):
+        return L.oracle_term_wide(p, n, i >> 64, i & M64)
+
+    A, p = _p(W.uniform_matrix(20, 960))
+    for a, c in [(0, 3000), (123456, 2000), ((1 << 20) - 900, 900)]:
+        if tally(p, 20, a, c) != oracle.range_tally(A, a, a + c):
+            return False
+    for n in (65, 128):
+        J, pJ = _p(W.rank_one_signs(n, 961 + n))
+        for a in (0, (1 << 63) - 300, (1 << 64) - 300, (1 << n) - 600, (1 << (n - 1)) + 12345):
+            if tally(pJ, n, a, 600) != sum(term(pJ, n, i) for i in range(a, a + 600)):
+                return False
+    for n1, n2 in ((6, 57), (8, 119), (6, 122)):
+        B, Mb, Db = W.wide_block(n1, n2, 962 + n2)
+        _, pB = _p(B)
+        delta = 1
+        for c in range(n2):
+            r = sum(-1 if int(x) == 2 else int(x) for x in Db[:, c]) % 3
+            delta *= -1 if r == 2 else r
+        h, x = 0, (1 << n2) - 1
+        while x:
+            h ^= x
+            x >>= 1
+        if tally(pB, n1 + n2, h << n1, 1 << n1) != (-1) ** n2 * delta * oracle.range_tally(Mb, 0, 1 << n1):
+            return False
+    return True
+
+
+def test_unmutated_oracle_passes_wide_pins(tmp_path):
+    L = _wide(_build(tmp_path, "original_wide", "#include <stdint.h>", "#include <stdint.h>"))
+    assert wide_pins_pass(L)
+
+
+@pytest.mark.parametrize("name", sorted(WIDE_MUTANTS))
+def test_wide_mutant_is_caught(tmp_path, name):
+    old, new = WIDE_MUTANTS[name]
+    L = _wide(_build(tmp_path, name, old, new))
+    assert not wide_pins_pass(L), f"planted mistake {name} slipped through the wide pins"
