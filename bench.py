@@ -9,7 +9,7 @@ n = 12..28, one persistent launch) against one launch per matrix, and the
 serving stream (20000 requests, n = 8..40, Poisson arrivals) with p50/p99
 latency against FIFO one-launch-per-request.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only headline|batch|serve]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--only headline|batch|serve|large|wide|...]
 """
 from __future__ import annotations
 
@@ -243,6 +243,53 @@ def bench_large(P, W, torch):
             "sparse40_result_counts": [int((sout == v).sum().item()) for v in range(3)]}
 
 
+# ------------------------------------------------------------------ 128 columns
+
+def gray_inverse(x: int) -> int:
+    """The Gray index whose state is x."""
+    i = 0
+    while x:
+        i ^= x
+        x >>= 1
+    return i
+
+
+def _time_wide(P, A, begin, count, steps, warmup):
+    P.timing_enable(True)
+    for _ in range(warmup):
+        P.perm_mod3_range_tally_wide(A, begin, count)
+    hot, wall = [], []
+    T = None
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        T = P.perm_mod3_range_tally_wide(A, begin, count)
+        wall.append(time.perf_counter() - t0)
+        hot.append(P.timing_last().hot_kernel_ms)
+    P.timing_enable(False)
+    hot_s = float(np.mean(hot)) * 1e-3
+    achieved = OPS_PER_TERM * count / hot_s
+    return {"indices": count, "tally": T,
+            "hot_kernel_ms_mean": float(np.mean(hot)), "hot_kernel_ms_min": float(np.min(hot)),
+            "call_ms_mean": 1e3 * float(np.mean(wall)), "terms_per_s": count / hot_s,
+            "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                         "unit": "T int32 lane-ops/s", "frac": achieved / PEAK_LANE_OPS, "kernel": "k_walk_wide"}}
+
+
+def bench_wide(P, W, steps=6, warmup=2):
+    """Matrices of 128 columns, 2^36 Gray indices per call (the headline's count) at indices near 2^127:
+    a uniform 128 x 128 matrix, and the block matrix M (+) D (M 36 x 36 hidden triangular, D 92 x 92)
+    on the range whose state holds every row of D, where T has a closed form."""
+    count = 1 << 36
+    U = W.uniform_matrix(128, W.SEED_WIDE)
+    uni = _time_wide(P, U, 3 << 125, count, steps, warmup)
+    uni["workload"] = "uniform 128x128 over F_3, 2^36 Gray indices from 3 * 2^125"
+    A, M, d, D = W.wide_128()
+    blk = _time_wide(P, A, gray_inverse((1 << 92) - 1) << 36, count, steps, warmup)
+    blk["workload"] = ("128x128 M (+) D: M hidden triangular 36x36, D 92x92, columns shuffled; 2^36 Gray "
+                       "indices from g^-1(all rows of D) * 2^36")
+    return {"n": 128, "uniform": uni, "block": blk}
+
+
 # ------------------------------------------------------------------ Pi_50 (Section 3.1)
 
 def bench_pi50(P, W, shards=64, ckdir=None):
@@ -413,7 +460,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["headline", "single20", "batch", "serve", "large", "pi50", "montecarlo"],
+    ap.add_argument("--only", choices=["headline", "single20", "batch", "serve", "large", "wide", "pi50",
+                                       "montecarlo"],
                     default=None)
     ap.add_argument("--mc-scale", type=float, default=0.01, help="fraction of Table 4's trial counts")
     ap.add_argument("--mc-n", default="6-30", help="range of n for the Monte Carlo study, e.g. 6-17")
@@ -484,6 +532,12 @@ def main():
         log(f"large: n=44 {lg['n44_s']:.3f} s ({lg['n44_terms_per_s']:.3e} terms/s), 64 sparse n=40 "
             f"{lg['sparse40_s']:.3f} s ({lg['sparse40_terms_per_s']:.3e} terms/s)")
         line["large"] = lg
+    if args.only in (None, "wide"):
+        wd = bench_wide(P, W)
+        for k in ("uniform", "block"):
+            log(f"wide {k}: n=128, 2^36 indices, walk {wd[k]['hot_kernel_ms_mean']:.3f} ms "
+                f"({wd[k]['terms_per_s']:.3e} indices/s, frac {wd[k]['roofline']['frac']:.3f})")
+        line["wide"] = wd
     if args.only == "montecarlo":
         lo, hi = (int(x) for x in args.mc_n.split("-"))
         line["montecarlo"] = bench_montecarlo(P, args.mc_scale, lo, hi)

@@ -145,7 +145,7 @@ struct WideArgs {
 
 constexpr int WIDE_MAX_N = 128;
 
-hipError_t launch_pack_wide(const uint8_t *A, int n, RowX *rows, uint64_t *queue, int64_t *tally,
+hipError_t launch_pack_wide(const uint8_t *A, int n, int vrows, RowX *rows, uint64_t *queue, int64_t *tally,
                             hipStream_t st);
 hipError_t launch_walk_wide(const WideArgs &a, int grid_blocks, hipStream_t st);
 

@@ -8,7 +8,8 @@
 // from scratch (exact_term on MasksX).  So an index costs what it costs at
 // n = 36, whatever the width.
 //
-//   k_pack_wide  phi of Section 2 over up to 128 columns; clears the range's
+//   k_pack_wide  phi of Section 2 over up to 128 columns, columns ordered so
+//                that the low word makes a good filter; clears the range's
 //                tally and task counter.
 //   k_walk_wide  persistent waves over 64-chunk tasks of one range; whole
 //                chunks take the unrolled fast walk, ragged ends (and small n)
@@ -28,20 +29,45 @@
 
 namespace perm3 {
 
-// phi on one row per thread: element j goes to bit n-1-j of the 128-bit row.
-__global__ void __launch_bounds__(128) k_pack_wide(const uint8_t *A, int n, RowX *rows, uint64_t *queue,
-                                                   int64_t *tally)
+// phi on one row per thread, with the columns reordered.  T(a, b) does not
+// depend on the order of the columns (each term is a product over all of
+// them), so the low 32-bit word, the only one the walk carries, is given the
+// columns most likely to be zero: those with the most non-zero entries among
+// the first vrows rows, the rows whose Gray bit varies over the range.  A
+// column with none there has the same sum at every index of the range and
+// can never reject one; such columns go last.  For a uniform matrix the order
+// hardly matters; for a matrix with fixed rows (a block whose rows are in
+// every subset of the range) it decides how often the low word passes.
+__global__ void __launch_bounds__(128) k_pack_wide(const uint8_t *A, int n, int vrows, RowX *rows,
+                                                   uint64_t *queue, int64_t *tally)
 {
-    const int r = threadIdx.x;
-    if (r == 0) {
+    __shared__ int s_cnt[WIDE_MAX_N];
+    __shared__ int s_pos[WIDE_MAX_N];
+    const int t = threadIdx.x;
+    if (t == 0) {
         *queue = 0;
         *tally = 0;
     }
-    if (r >= n) return;
+    if (t < n) {
+        int c = 0;
+        for (int r = 0; r < vrows; ++r) c += A[r * n + t] != 0;
+        s_cnt[t] = c;
+    }
+    __syncthreads();
+    if (t < n) {
+        // the column's bit: its rank by decreasing count, ties by column index
+        const int c = s_cnt[t];
+        int pos = 0;
+        for (int j = 0; j < n; ++j) pos += (s_cnt[j] > c) || (s_cnt[j] == c && j < t);
+        s_pos[t] = pos;
+    }
+    __syncthreads();
+    if (t >= n) return;
+    const int r = t;
     uint64_t mag[2] = {0, 0}, sgn[2] = {0, 0};
     for (int j = 0; j < n; ++j) {
         const uint8_t v = A[r * n + j];
-        const int p = n - 1 - j;
+        const int p = s_pos[j];
         const uint64_t bit = 1ull << (p & 63);
         if (v != 0) mag[p >> 6] |= bit;
         if (v == 2) sgn[p >> 6] |= bit;
@@ -92,10 +118,11 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_wide(WideArgs a)
     }
 }
 
-hipError_t launch_pack_wide(const uint8_t *A, int n, RowX *rows, uint64_t *queue, int64_t *tally, hipStream_t st)
+hipError_t launch_pack_wide(const uint8_t *A, int n, int vrows, RowX *rows, uint64_t *queue, int64_t *tally,
+                            hipStream_t st)
 {
-    if (n < 1 || n > WIDE_MAX_N) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_pack_wide, dim3(1), dim3(128), 0, st, A, n, rows, queue, tally);
+    if (n < 1 || n > WIDE_MAX_N || vrows < 0 || vrows > n) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_pack_wide, dim3(1), dim3(128), 0, st, A, n, vrows, rows, queue, tally);
     return hipGetLastError();
 }
 
@@ -202,7 +229,12 @@ extern "C" int32_t perm_mod3_range_tally_wide(const uint8_t *A, int32_t n, uint6
     const bool timed = timing_enabled();
     if (timed) WIDE_TRY(hipEventRecord(c->ev_all0, st));
     WIDE_TRY(hipMemcpyAsync(d, h, mat_bytes, hipMemcpyHostToDevice, st));
-    WIDE_TRY(launch_pack_wide(d, n, (RowX *)(d + rows_at), a.queue, a.tally, st));
+    // rows whose Gray bit varies over the range: bits below the highest bit in
+    // which the first and last index differ
+    const u128 diff = begin ^ (begin + (count - 1));
+    const uint64_t dh = (uint64_t)(diff >> 64), dl = (uint64_t)diff;
+    const int varying = dh ? 128 - __builtin_clzll(dh) : (dl ? 64 - __builtin_clzll(dl) : 0);
+    WIDE_TRY(launch_pack_wide(d, n, std::min(varying, n), (RowX *)(d + rows_at), a.queue, a.tally, st));
     if (timed) WIDE_TRY(hipEventRecord(c->ev_walk0, st));
     const uint64_t want_blocks = (a.ntasks + 3) / 4;
     const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(want_blocks, (uint64_t)c->grid_blocks()));

@@ -132,6 +132,39 @@ def test_wide_128_workload():
     assert sum(P.perm_mod3_range_tally_wide(A, begin + k * q, q) for k in range(4)) == T
 
 
+def test_wide_uniform_128_workload():
+    """The uniform 128 x 128 matrix the benchmark times, 2^36 indices from 3 * 2^125: sampled pieces
+    against the oracle, and shards that add up to the whole (T is 0 here: a non-zero term needs
+    all 128 column sums non-zero, a (2/3)^128 event)."""
+    U = W.uniform_matrix(128, W.SEED_WIDE)
+    begin = 3 << 125
+    T = P.perm_mod3_range_tally_wide(U, begin, 1 << 36)
+    r = random.Random(11)
+    pieces = [(begin + r.randrange(1 << 36), (1 << 17) + k) for k in range(8)]
+    want = oracle_wide(U, pieces)
+    for (a, c), w in zip(pieces, want):
+        assert P.perm_mod3_range_tally_wide(U, a, c) == w, (hex(a), c)
+    q = 1 << 33
+    assert sum(P.perm_mod3_range_tally_wide(U, begin + k * q, q) for k in range(8)) == T
+
+
+def test_wide_column_order_does_not_matter():
+    """The library reorders columns for its filter; T is a product over all columns, so any
+    permutation of the columns, and any range, gives the same tally."""
+    A, M, D = W.wide_block(24, 90, 1400)
+    h = gray_inverse((1 << 90) - 1)
+    ref = P.perm_mod3_range_tally_wide(A, h << 24, 1 << 24)
+    g = W.rng(1401)
+    for _ in range(3):
+        B = np.ascontiguousarray(A[:, g.permutation(114)])
+        assert P.perm_mod3_range_tally_wide(B, h << 24, 1 << 24) == ref
+    J = W.rank_one_signs(128, 1402)
+    a = (1 << 127) + 999
+    ref = P.perm_mod3_range_tally_wide(J, a, 1 << 15)
+    assert ref == oracle.range_tally_wide(J, a, 1 << 15, threads=host_threads())
+    assert P.perm_mod3_range_tally_wide(np.ascontiguousarray(J[:, ::-1]), a, 1 << 15) == ref
+
+
 def test_wide_tuning_does_not_change_tallies():
     A = W.rank_one_signs(100, 1300)
     B, M, D = W.wide_block(20, 100, 1301)
