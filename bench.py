@@ -290,6 +290,68 @@ def bench_wide(P, W, steps=6, warmup=2):
     return {"n": 128, "uniform": uni, "block": blk}
 
 
+# ------------------------------------------------------------------ vectors over F_3
+
+HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
+
+
+def bench_vec(P, torch, log2_len=32, reps=10):
+    """Bitsliced F_3 vectors of 2^32 elements in HBM: phi, Theorem 2.1's add and mul, the dot
+    product and psi, each timed by HIP events on one stream, against the HBM peak."""
+    n = 1 << log2_len
+    words = P.f3_words(n)
+    t = torch
+    gen = t.Generator(device="cuda")
+    gen.manual_seed(7)
+    va = t.randint(0, 3, (n,), dtype=t.uint8, device="cuda", generator=gen)
+    vb = t.randint(0, 3, (n,), dtype=t.uint8, device="cuda", generator=gen)
+    pa = t.empty(2 * words, dtype=t.int64, device="cuda")
+    pb = t.empty_like(pa)
+    po = t.empty_like(pa)
+    back = t.empty(n, dtype=t.uint8, device="cuda")
+    s = t.zeros(1, dtype=t.int64, device="cuda")
+    st = t.cuda.current_stream()
+    plane_bytes = 16 * words
+    cases = {
+        # name: (call, algorithmic HBM bytes: each operand read once, each result written once)
+        "pack": (lambda: P.f3_pack(va, pa, None, st), n + plane_bytes),
+        "add": (lambda: P.f3_op(P.PERM_F3_ADD, pa, pb, po, stream=st), 3 * plane_bytes),
+        "mul": (lambda: P.f3_op(P.PERM_F3_MUL, pa, pb, po, stream=st), 3 * plane_bytes),
+        "dot": (lambda: P.f3_dot(pa, pb, s, stream=st), 2 * plane_bytes),
+        "unpack": (lambda: P.f3_unpack(po, n, back, stream=st), plane_bytes + n),
+    }
+    P.f3_pack(vb, pb, None, st)
+    out = {"workload": f"two uniform vectors of 2^{log2_len} elements over F_3 (bytes), "
+                       f"bipedal planes of {plane_bytes} bytes each"}
+    for name, (call, nbytes) in cases.items():
+        for _ in range(2):
+            call()
+        e0, e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            call()
+        e1.record(st)
+        e1.synchronize()
+        sec = e0.elapsed_time(e1) * 1e-3 / reps
+        out[name] = {"ms": sec * 1e3, "bytes": nbytes, "GB_per_s": nbytes / sec / 1e9,
+                     "roofline": {"bound": "hbm", "achieved": nbytes / sec / 1e9, "peak": HBM_PEAK / 1e9,
+                                  "unit": "GB/s", "frac": nbytes / sec / HBM_PEAK}}
+    out["dot_value"] = int(s.item())
+    del pa, pb, po, back
+    # what a plain device-to-device copy of the same 2^32 bytes reaches on this GPU (read + write)
+    for _ in range(2):
+        vb.copy_(va)
+    e0, e1 = t.cuda.Event(enable_timing=True), t.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        vb.copy_(va)
+    e1.record(st)
+    e1.synchronize()
+    out["device_copy_GB_per_s"] = 2 * n / (e0.elapsed_time(e1) * 1e-3 / reps) / 1e9
+    del va, vb
+    return out
+
+
 # ------------------------------------------------------------------ Pi_50 (Section 3.1)
 
 def bench_pi50(P, W, shards=64, ckdir=None):
@@ -460,7 +522,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["headline", "single20", "batch", "serve", "large", "wide", "pi50",
+    ap.add_argument("--only", choices=["headline", "single20", "batch", "serve", "large", "wide", "vec", "pi50",
                                        "montecarlo"],
                     default=None)
     ap.add_argument("--mc-scale", type=float, default=0.01, help="fraction of Table 4's trial counts")
@@ -538,6 +600,11 @@ def main():
             log(f"wide {k}: n=128, 2^36 indices, walk {wd[k]['hot_kernel_ms_mean']:.3f} ms "
                 f"({wd[k]['terms_per_s']:.3e} indices/s, frac {wd[k]['roofline']['frac']:.3f})")
         line["wide"] = wd
+    if args.only in (None, "vec"):
+        vc = bench_vec(P, torch)
+        log("vec: " + ", ".join(f"{k} {vc[k]['GB_per_s']:.0f} GB/s" for k in ("pack", "add", "mul", "dot", "unpack")) +
+            f"; device copy {vc['device_copy_GB_per_s']:.0f} GB/s")
+        line["vec"] = vc
     if args.only == "montecarlo":
         lo, hi = (int(x) for x in args.mc_n.split("-"))
         line["montecarlo"] = bench_montecarlo(P, args.mc_scale, lo, hi)

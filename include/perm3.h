@@ -99,6 +99,45 @@ int32_t perm_mod3_range_tally_wide(const uint8_t *A, int32_t n, uint64_t begin_h
                                    uint64_t count, int64_t *tally);
 
 /* --------------------------------------------------------------------------
+ * Bitsliced vectors over F_3 in device memory (Theorem 2.1 in full).
+ *
+ * A vector of len elements is held as ceil(len/64) word pairs:
+ * planes[2w] = mag and planes[2w+1] = sgn of elements 64w .. 64w+63, element
+ * e at bit e mod 64 (least significant first), under phi of Section 2:
+ * 0 -> (0,0), 1 -> (1,0), -1 -> (1,1), and (0,1) is also 0.  Bits at and
+ * above len in the last word are 0 after perm_f3_pack.  (Any bit order is
+ * valid for perm_mod3_batch_packed's rows, since a permanent does not depend
+ * on the order of the columns.)  Every pointer is device memory; planes must
+ * be 16-byte aligned.  Calls are asynchronous on `stream` (a hipStream_t;
+ * NULL is the legacy default stream) and return after enqueueing.
+ */
+#define PERM_F3_ADD 0   /* a + b, Theorem 2.1 as printed                         */
+#define PERM_F3_SUB 1   /* a - b, Theorem 2.1 as printed                         */
+#define PERM_F3_MUL 2   /* elementwise a * b                                     */
+#define PERM_F3_DIV 3   /* elementwise a / b where b != 0; where b = 0 unspecified */
+#define PERM_F3_NEG 4   /* -a (b is not read and may be NULL)                    */
+#define PERM_F3_MAX_LEN (1ll << 40)
+
+/* phi: v_dev bytes in {0,1,2} (2 = -1) -> planes_dev[2 * ceil(len/64)].  A
+ * byte > 2 is packed as 0 and counted: the count is ADDED to *invalid_dev
+ * (device uint64, may be NULL).  0 <= len <= PERM_F3_MAX_LEN. */
+int32_t perm_f3_pack(const uint8_t *v_dev, int64_t len, uint64_t *planes_dev, uint64_t *invalid_dev,
+                     void *stream);
+
+/* psi: planes_dev -> v_dev[len] bytes in {0,1,2}; (0,1) reads as 0. */
+int32_t perm_f3_unpack(const uint64_t *planes_dev, int64_t len, uint8_t *v_dev, void *stream);
+
+/* out = a op b over `words` word pairs (out may alias a or b).  The result's
+ * bits are those of Theorem 2.1's formulas, so a zero may come out as (0,1). */
+int32_t perm_f3_op(int32_t op, const uint64_t *a_dev, const uint64_t *b_dev, uint64_t *out_dev, int64_t words,
+                   void *stream);
+
+/* *sum_dev (device int64) = sum over the elements of a_e * b_e as integers in
+ * {-1,0,1}; the dot product over F_3 is that sum mod 3.  Bits beyond a
+ * vector's length must be 0 in mag (as perm_f3_pack leaves them). */
+int32_t perm_f3_dot(const uint64_t *a_dev, const uint64_t *b_dev, int64_t words, int64_t *sum_dev, void *stream);
+
+/* --------------------------------------------------------------------------
  * Many matrices in one persistent launch.
  *
  * perm_mod3_batch: As[k] is a host pointer to the k-th n_k x n_k matrix,

@@ -14,6 +14,8 @@ Two independent definitions live here:
   with its cmod3 reduction), threaded over blocks of consecutive Gray indices
   as in Section 3.1.  It returns exact partial tallies T(a, b) and perm mod 3,
   and, for matrices of up to 128 columns, tallies over 128-bit Gray indices.
+* vectors over F_3 (``f3_*``): phi and psi of Section 2 and elementwise
+  arithmetic of F_3 on unpacked values, the definitions behind Theorem 2.1.
 
 Inputs are n x n uint8 matrices with entries in {0, 1, 2}; 2 stands for -1.
 """
@@ -80,6 +82,15 @@ def lib():
         L.oracle_range_tally_wide_mt.argtypes = [u8p, ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64,
                                                  ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.oracle_range_tally_wide_mt.restype = ctypes.c_int64
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        L.oracle_f3_phi.argtypes = [u8p, ctypes.c_int64, u64p]
+        L.oracle_f3_phi.restype = ctypes.c_int64
+        L.oracle_f3_psi.argtypes = [u64p, ctypes.c_int64, u8p]
+        L.oracle_f3_psi.restype = None
+        L.oracle_f3_op.argtypes = [ctypes.c_int, u8p, u8p, ctypes.c_int64, u8p]
+        L.oracle_f3_op.restype = ctypes.c_int
+        L.oracle_f3_dot.argtypes = [u8p, u8p, ctypes.c_int64]
+        L.oracle_f3_dot.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -172,6 +183,54 @@ def range_tally_wide(A, begin: int, count: int, threads: int | None = None) -> i
     if not ok.value:
         raise ValueError("invalid matrix or range")
     return int(v)
+
+
+def _vec(v) -> np.ndarray:
+    v = np.ascontiguousarray(np.asarray(v, dtype=np.uint8))
+    if v.ndim != 1:
+        raise ValueError("vector expected")
+    return v
+
+
+def f3_phi(v) -> tuple[np.ndarray, int]:
+    """phi of a vector: (planes uint64[2 * ceil(len/64)], count of bytes > 2); element e at bit e mod 64."""
+    v = _vec(v)
+    planes = np.zeros(2 * ((len(v) + 63) // 64), dtype=np.uint64)
+    bad = lib().oracle_f3_phi(_ptr(v), len(v), planes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)))
+    return planes, int(bad)
+
+
+def f3_psi(planes, length: int) -> np.ndarray:
+    """psi of bipedal planes back to bytes {0, 1, 2}."""
+    planes = np.ascontiguousarray(np.asarray(planes, dtype=np.uint64))
+    if planes.size < 2 * ((length + 63) // 64):
+        raise ValueError("planes too short")
+    out = np.zeros(length, dtype=np.uint8)
+    lib().oracle_f3_psi(planes.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), length, _ptr(out))
+    return out
+
+
+F3_ADD, F3_SUB, F3_MUL, F3_DIV, F3_NEG = range(5)
+
+
+def f3_op(op: int, a, b=None) -> np.ndarray:
+    """Elementwise a op b in F_3 on bytes (2 = -1); a quotient by 0 comes out as 0xFF."""
+    a = _vec(a)
+    b = a if b is None else _vec(b)
+    if len(b) != len(a):
+        raise ValueError("lengths differ")
+    out = np.zeros(len(a), dtype=np.uint8)
+    if lib().oracle_f3_op(op, _ptr(a), _ptr(b), len(a), _ptr(out)) != 0:
+        raise ValueError("bad op or entry")
+    return out
+
+
+def f3_dot(a, b) -> int:
+    """sum_e a_e b_e over the integers, entries read in {-1, 0, 1}."""
+    a, b = _vec(a), _vec(b)
+    if len(b) != len(a):
+        raise ValueError("lengths differ")
+    return int(lib().oracle_f3_dot(_ptr(a), _ptr(b), len(a)))
 
 
 def signed(A) -> list[list[int]]:

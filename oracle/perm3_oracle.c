@@ -432,3 +432,81 @@ int64_t oracle_range_tally_wide_mt(const uint8_t *A, int n, uint64_t a_hi, uint6
     if (ok) *ok = all_ok;
     return s;
 }
+
+/* ------------------------------------------------------------------ */
+/* Vectors over F_3 (Section 2 and Theorem 2.1 beyond the permanent): the
+ * definitions, on unpacked values.  A vector is bytes in {0,1,2} (2 = -1).
+ * Its bipedal form is ceil(len/64) word pairs, planes[2w] = mag and
+ * planes[2w+1] = sgn, element e at bit e mod 64 of word e / 64.           */
+
+/* The element of F_3 named by 0, 1 or -1 as a byte. */
+static uint8_t f3_byte(int x)
+{
+    int r = centred_mod3(x);
+    return r < 0 ? 2 : (uint8_t)r;
+}
+
+static int f3_value(uint8_t b) { return b == 2 ? -1 : (int)b; }
+
+/* phi of Section 2: 0 -> (0,0), 1 -> (1,0), -1 -> (1,1).  Bytes > 2 are left
+ * as (0,0) and counted; the count is returned. */
+int64_t oracle_f3_phi(const uint8_t *v, int64_t len, uint64_t *planes)
+{
+    int64_t words = (len + 63) / 64, bad = 0;
+    for (int64_t w = 0; w < 2 * words; ++w) planes[w] = 0;
+    for (int64_t e = 0; e < len; ++e) {
+        uint64_t bit = (uint64_t)1 << (e % 64);
+        if (v[e] > 2) { ++bad; continue; }
+        if (v[e] != 0) planes[2 * (e / 64)] |= bit;        /* magnitude: non-zero */
+        if (v[e] == 2) planes[2 * (e / 64) + 1] |= bit;    /* sign: -1 */
+    }
+    return bad;
+}
+
+/* psi of Section 2: magnitude 0 is 0 whatever the sign bit; else the sign bit
+ * chooses between 1 and -1. */
+void oracle_f3_psi(const uint64_t *planes, int64_t len, uint8_t *v)
+{
+    for (int64_t e = 0; e < len; ++e) {
+        int m = (int)((planes[2 * (e / 64)] >> (e % 64)) & 1u);
+        int s = (int)((planes[2 * (e / 64) + 1] >> (e % 64)) & 1u);
+        v[e] = m ? (s ? 2 : 1) : 0;
+    }
+}
+
+/* out_e = a_e op b_e in F_3; op 0 add, 1 subtract, 2 multiply, 3 divide,
+ * 4 negate a.  Division multiplies by the inverse found from its definition
+ * (the y with b y = 1); where b_e = 0 the quotient is undefined and out_e is
+ * 0xFF.  Returns -1 for an unknown op or an entry > 2. */
+int oracle_f3_op(int op, const uint8_t *a, const uint8_t *b, int64_t len, uint8_t *out)
+{
+    if (op < 0 || op > 4) return -1;
+    for (int64_t e = 0; e < len; ++e) {
+        if (a[e] > 2 || (op != 4 && b[e] > 2)) return -1;
+        int x = f3_value(a[e]);
+        int y = op == 4 ? 0 : f3_value(b[e]);
+        switch (op) {
+        case 0: out[e] = f3_byte(x + y); break;
+        case 1: out[e] = f3_byte(x - y); break;
+        case 2: out[e] = f3_byte(x * y); break;
+        case 3: {
+            int inv = 0;
+            for (int c = -1; c <= 1; ++c)
+                if (centred_mod3(y * c) == 1) inv = c;
+            out[e] = inv ? f3_byte(x * inv) : 0xFF;
+            break;
+        }
+        default: out[e] = f3_byte(-x); break;
+        }
+    }
+    return 0;
+}
+
+/* sum over e of a_e * b_e as integers in {-1,0,1} (the F_3 dot product is
+ * this mod 3). */
+int64_t oracle_f3_dot(const uint8_t *a, const uint8_t *b, int64_t len)
+{
+    int64_t s = 0;
+    for (int64_t e = 0; e < len; ++e) s += (int64_t)f3_value(a[e]) * f3_value(b[e]);
+    return s;
+}

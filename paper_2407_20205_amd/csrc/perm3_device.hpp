@@ -46,6 +46,14 @@ __device__ __forceinline__ int wave_sum(int v)
            __builtin_amdgcn_readlane(v, 47) + __builtin_amdgcn_readlane(v, 63);
 }
 
+// The same for 64-bit values, by butterfly shuffles.  Every lane must be active.
+__device__ __forceinline__ long long wave_sum_i64(long long v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
 // r = ((-1)^n * T) mod 3 in {0, 1, 2} (2 stands for -1).
 __device__ __forceinline__ uint8_t finish_mod3(int n, long long T)
 {

@@ -30,6 +30,12 @@ PERM_ESTATE = -6
 PERM_RESULT_INVALID = 0xFF
 PERM_GEN_ENUMERATE = 0
 PERM_GEN_SPLITMIX = 1
+PERM_F3_ADD = 0
+PERM_F3_SUB = 1
+PERM_F3_MUL = 2
+PERM_F3_DIV = 3
+PERM_F3_NEG = 4
+PERM_F3_MAX_LEN = 1 << 40
 PERM_POLICY_SRPT = 0
 PERM_POLICY_FIFO = 1
 
@@ -92,6 +98,10 @@ EXPORTS = [
     ("perm_mod3", _i32, [_vp, _i32, _vp]),
     ("perm_mod3_range_tally", _i32, [_vp, _i32, ctypes.c_uint64, ctypes.c_uint64, _vp]),
     ("perm_mod3_range_tally_wide", _i32, [_vp, _i32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _vp]),
+    ("perm_f3_pack", _i32, [_vp, ctypes.c_int64, _vp, _vp, _vp]),
+    ("perm_f3_unpack", _i32, [_vp, ctypes.c_int64, _vp, _vp]),
+    ("perm_f3_op", _i32, [_i32, _vp, _vp, _vp, ctypes.c_int64, _vp]),
+    ("perm_f3_dot", _i32, [_vp, _vp, ctypes.c_int64, _vp, _vp]),
     ("perm_mod3_batch", _i32, [_vp, _vp, _i32, _vp]),
     ("perm_mod3_batch_dev", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     ("perm_mod3_batch_packed", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
@@ -225,6 +235,37 @@ def perm_mod3_batch_packed(planes_dev, row_off_dev, ns_dev, out_dev, hist_dev=No
     count = int(ns_dev.numel())
     _check(lib().perm_mod3_batch_packed(_dptr(planes_dev), _dptr(row_off_dev), _dptr(ns_dev), count,
                                         _dptr(out_dev), _dptr(hist_dev), _stream(stream)))
+
+
+# ---------------------------------------------------------------- vectors over F_3 (device tensors)
+
+def f3_words(length: int) -> int:
+    """Word pairs of a bipedal vector of `length` elements."""
+    return (length + 63) // 64
+
+
+def f3_pack(v_dev, planes_dev, invalid_dev=None, stream=None) -> None:
+    """phi: uint8 tensor v_dev (values 0, 1, 2) into int64 planes_dev[2 * f3_words(len)]; bytes > 2 are
+    packed as 0 and their count is added to invalid_dev[0] (int64/uint64 tensor) when given."""
+    _check(lib().perm_f3_pack(_dptr(v_dev), int(v_dev.numel()), _dptr(planes_dev), _dptr(invalid_dev),
+                              _stream(stream)))
+
+
+def f3_unpack(planes_dev, length: int, v_dev, stream=None) -> None:
+    """psi: planes into uint8 v_dev[length]."""
+    _check(lib().perm_f3_unpack(_dptr(planes_dev), length, _dptr(v_dev), _stream(stream)))
+
+
+def f3_op(op: int, a_dev, b_dev, out_dev, words: int | None = None, stream=None) -> None:
+    """out = a op b (Theorem 2.1) over `words` word pairs (default: all of a)."""
+    w = int(a_dev.numel()) // 2 if words is None else words
+    _check(lib().perm_f3_op(op, _dptr(a_dev), _dptr(b_dev), _dptr(out_dev), w, _stream(stream)))
+
+
+def f3_dot(a_dev, b_dev, sum_dev, words: int | None = None, stream=None) -> None:
+    """sum_dev[0] (int64 tensor) = sum_e a_e b_e over the integers; the F_3 dot product is it mod 3."""
+    w = int(a_dev.numel()) // 2 if words is None else words
+    _check(lib().perm_f3_dot(_dptr(a_dev), _dptr(b_dev), w, _dptr(sum_dev), _stream(stream)))
 
 
 # ---------------------------------------------------------------- tuning, timing, device

@@ -180,3 +180,81 @@ def test_wide_mutant_is_caught(tmp_path, name):
     old, new = WIDE_MUTANTS[name]
     L = _wide(_build(tmp_path, name, old, new))
     assert not wide_pins_pass(L), f"planted mistake {name} slipped through the wide pins"
+
+
+# ---------------------------------------------------------------- vectors over F_3
+
+F3_MUTANTS = {
+    "f3_phi_sign_on_one": ("if (v[e] == 2) planes[2 * (e / 64) + 1] |= bit;",
+                           "if (v[e] != 0) planes[2 * (e / 64) + 1] |= bit;"),
+    "f3_phi_msb_first": ("uint64_t bit = (uint64_t)1 << (e % 64);",
+                         "uint64_t bit = (uint64_t)1 << (63 - e % 64);"),
+    "f3_sub_reversed": ("case 1: out[e] = f3_byte(x - y); break;", "case 1: out[e] = f3_byte(y - x); break;"),
+    "f3_div_negated": ("out[e] = inv ? f3_byte(x * inv) : 0xFF;", "out[e] = inv ? f3_byte(-x * inv) : 0xFF;"),
+    "f3_psi_second_zero_as_minus_one": ("v[e] = m ? (s ? 2 : 1) : 0;", "v[e] = m ? (s ? 2 : 1) : (s ? 2 : 0);"),
+    "f3_dot_ignores_sign": ("s += (int64_t)f3_value(a[e]) * f3_value(b[e]);",
+                            "s += (int64_t)(a[e] != 0) * (b[e] != 0);"),
+}
+
+
+def _f3(L):
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    L.oracle_f3_phi.argtypes = [u8p, ctypes.c_int64, u64p]
+    L.oracle_f3_phi.restype = ctypes.c_int64
+    L.oracle_f3_psi.argtypes = [u64p, ctypes.c_int64, u8p]
+    L.oracle_f3_psi.restype = None
+    L.oracle_f3_op.argtypes = [ctypes.c_int, u8p, u8p, ctypes.c_int64, u8p]
+    L.oracle_f3_op.restype = ctypes.c_int
+    L.oracle_f3_dot.argtypes = [u8p, u8p, ctypes.c_int64]
+    L.oracle_f3_dot.restype = ctypes.c_int64
+    return L
+
+
+def f3_pins_pass(L) -> bool:
+    """The pins of test_oracle_f3.py on a mutated copy: the hand-written tables, the worked
+    example of Section 2, psi after phi (with the second zero), the dot product's closed forms."""
+    from conftest import read_golden
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    ops = {"add": 0, "sub": 1, "mul": 2, "div": 3}
+    byte = lambda x: 2 if x == -1 else x
+    out = np.zeros(1, np.uint8)
+    for op, a, b, r in read_golden("f3_tables.txt"):
+        va, pa = _p(np.array([byte(int(a))]))
+        vb, pb = _p(np.array([byte(int(b))]))
+        L.oracle_f3_op(ops[op], pa, pb, 1, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+        if out[0] != byte(int(r)):
+            return False
+    (vec, mag, sgn, _), = read_golden("phi_worked_example.txt")
+    v, pv = _p(np.array([int(x) for x in vec.split(",")]))
+    planes = np.zeros(2, np.uint64)
+    L.oracle_f3_phi(pv, 4, planes.ctypes.data_as(u64p))
+    rev = lambda x: int(format(x, "04b")[::-1], 2)
+    if planes.tolist() != [rev(int(mag, 16)), rev(int(sgn, 16))]:
+        return False
+    back = np.zeros(4, np.uint8)
+    second_zero = np.array([0b0110, 0b1100], np.uint64)
+    L.oracle_f3_psi(second_zero.ctypes.data_as(u64p), 4, back.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    if back.tolist() != [0, 1, 2, 0]:
+        return False
+    g = W.rng(977)
+    a, pa = _p(g.integers(0, 3, 300))
+    b, pb = _p(g.integers(0, 3, 300))
+    if L.oracle_f3_dot(pa, pa, 300) != int((a != 0).sum()):
+        return False
+    ones, po = _p(np.ones(300))
+    if L.oracle_f3_dot(pa, po, 300) != int((a == 1).sum()) - int((a == 2).sum()):
+        return False
+    return True
+
+
+def test_unmutated_oracle_passes_f3_pins(tmp_path):
+    L = _f3(_build(tmp_path, "original_f3", "#include <stdint.h>", "#include <stdint.h>"))
+    assert f3_pins_pass(L)
+
+
+@pytest.mark.parametrize("name", sorted(F3_MUTANTS))
+def test_f3_mutant_is_caught(tmp_path, name):
+    old, new = F3_MUTANTS[name]
+    L = _f3(_build(tmp_path, name, old, new))
+    assert not f3_pins_pass(L), f"planted mistake {name} slipped through the F_3 pins"
