@@ -195,6 +195,26 @@ PERM3_FN int rewalk_exact(RP R, int n, I ia, I ib, uint32_t ml, uint32_t sl, con
     return tally;
 }
 
+// Exact re-walk of a block backwards: (ml, sl) is the low-word state at
+// Gray index ib; indices ib, ib-1, .. ia+1 are tested, each step undone by
+// adding back what the step into it removed (or removing what it added).  An
+// undone step may leave a zero as (0,1) where the forward walk had (0,0); the
+// test reads only mag and, where every mag bit is set, sgn, and neither
+// depends on how a zero is represented.
+template <typename RP, typename I, typename MK>
+PERM3_FN int rewalk_back(RP R, int n, I ia, I ib, uint32_t ml, uint32_t sl, const MK &mk)
+{
+    int tally = 0;
+    for (I i = ib; i != ia; --i) {
+        tally += exact_term(R, n, i, ml, sl, mk);
+        const uint64_t il = (uint64_t)i;
+        const int t = __builtin_ctzll(il);
+        const bool left = (il >> (t + 1)) & 1u;   // the step into i removed row t
+        bip_add(ml, sl, R[t].m_lo, left ? R[t].s_lo : R[t].sn_lo);
+    }
+    return tally;
+}
+
 // Fast walk of S whole aligned chunks c + 64 s (s = 0 .. S-1) of length
 // 2^m, m > UL, carried side by side in one lane.
 //
@@ -215,7 +235,8 @@ PERM3_FN int rewalk_exact(RP R, int n, I ia, I ib, uint32_t ml, uint32_t sl, con
 // each low mag word is <= mk.lo, so the block's maximum equals mk.lo exactly
 // when some index in it has all its low columns non-zero (one 3-input max
 // per two states, or per two steps when S = 1).  Only then is the block
-// walked again exactly (rewalk_exact from the state saved at its first index).
+// walked again exactly, backwards from its end state (rewalk_back), so the
+// block keeps no copy of the state it started from.
 //
 // The chunk index c is a uint64_t for n <= 63 and a u128 for wider matrices
 // (with MasksX); only the seed and the exact terms see its high bits.
@@ -251,12 +272,6 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const Stati
             const bool leave = (jb >> (tb + 1 - UL)) & 1u;
             const uint32_t bm = PERM3_TO_VGPR(inner ? R[tb].m_lo : 0u);
             const uint32_t bs = PERM3_TO_VGPR(inner ? (leave ? R[tb].sn_lo : R[tb].s_lo) : 0u);
-            uint32_t m0[S], s0[S];
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                m0[q] = ml[q];
-                s0[q] = sl[q];
-            }
             uint32_t acc = 0;
 #pragma unroll
             for (int k = 1; k <= (int)U; ++k) {
@@ -290,7 +305,7 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const Stati
 #pragma unroll
                 for (int q = 0; q < S; ++q) {
                     const I i0 = (c + (I)(64u * q)) << m;
-                    tally += rewalk_exact(R, n, i0 + b * U, i0 + last, m0[q], s0[q], mk);
+                    tally += rewalk_back(R, n, i0 + b * U, i0 + last, ml[q], sl[q], mk);
                 }
             }
         }
