@@ -38,9 +38,9 @@ OPS_PER_TERM = 3.5
 PAPER_OPS_PER_TERM_2W = 14
 
 
-def measured_traffic():
-    """HBM bytes per walk launch from the committed counter passes (FETCH_SIZE and WRITE_SIZE,
-    each scaled by a 256 MiB copy); None once the kernel source differs from the profiled one."""
+def walk_counters():
+    """The committed counter passes of the 36x36 walk (profiles/k_walk_36x36_counters.json), or None
+    once the kernel source differs from the profiled one."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_walk_36x36_counters.json")
     try:
@@ -52,7 +52,13 @@ def measured_traffic():
     for name in ("perm3_walk.hpp", "perm3_kernels.hip"):
         with open(os.path.join(ROOT, "paper_2407_20205_amd", "csrc", name), "rb") as f:
             h.update(f.read())
-    return d["traffic_bytes_per_launch"] if h.hexdigest() == d.get("source_sha256") else None
+    return d if h.hexdigest() == d.get("source_sha256") else None
+
+
+def measured_traffic():
+    """HBM bytes per walk launch (FETCH_SIZE and WRITE_SIZE, each scaled by a 256 MiB copy)."""
+    d = walk_counters()
+    return d["traffic_bytes_per_launch"] if d else None
 
 
 def log(*a):
@@ -93,7 +99,7 @@ def bench_headline(P, W, torch, steps, warmup):
     sec = t1 - t0
     hot_s = float(np.mean(hot)) * 1e-3
     achieved = OPS_PER_TERM * terms / hot_s
-    return {
+    res = {
         "terms_per_s": steps * terms / sec,
         "ms_per_step": 1e3 * sec / steps,
         "hot_kernel_ms_mean": float(np.mean(hot)),
@@ -113,6 +119,14 @@ def bench_headline(P, W, torch, steps, warmup):
         },
         "paper_ops_frac": PAPER_OPS_PER_TERM_2W * terms / hot_s / PEAK_LANE_OPS,
     }
+    d = walk_counters()
+    if d:
+        # executed VALU lane-ops (SQ_INSTS_VALU x 64 per index, from the counter pass) over the peak,
+        # and rocprof's VALUUtilization
+        res["roofline"]["executed_frac"] = d["valu_lane_ops_per_term"] * terms / hot_s / PEAK_LANE_OPS
+        if "valu_utilization_pct" in d:
+            res["roofline"]["valu_utilization_pct"] = d["valu_utilization_pct"]
+    return res
 
 
 # ------------------------------------------------------------------ batch

@@ -121,6 +121,7 @@ hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st);
 hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st);
 hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st);
 hipError_t launch_tick(const TickArgs &a, int grid_blocks, hipStream_t st);
+int walk_resident_per_cu(int states);   // k_walk<states> workgroups per CU at once; 0: k_tick
 hipError_t launch_finish(const FinishArgs &a, int max_fin, hipStream_t st);
 hipError_t launch_slot_pack(const uint8_t *A, int n, RowW *dst, hipStream_t st);
 hipError_t launch_bipedal_ops(const uint32_t *in, int count, uint32_t *out, hipStream_t st);
@@ -148,6 +149,7 @@ constexpr int WIDE_MAX_N = 128;
 hipError_t launch_pack_wide(const uint8_t *A, int n, int vrows, RowX *rows, uint64_t *queue, int64_t *tally,
                             hipStream_t st);
 hipError_t launch_walk_wide(const WideArgs &a, int grid_blocks, hipStream_t st);
+int wide_resident_per_cu();             // k_walk_wide workgroups per CU at once
 
 }  // namespace perm3
 

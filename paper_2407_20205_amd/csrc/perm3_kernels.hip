@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "perm3_device.hpp"
 #include "perm3_internal.h"
 #include "perm3_walk.hpp"
@@ -475,6 +477,31 @@ hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st)
     if (a.count <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_pack_planes, dim3(a.count), dim3(64), 0, st, a);
     return hipGetLastError();
+}
+
+// Workgroups of a kernel that fit on one CU at once.  A persistent wave's first
+// task is its own index, so a workgroup that is not resident at launch would
+// start its first task only when an earlier one exits, at the end of the run:
+// the walk grids are capped at this count.
+template <typename K>
+static int resident_per_cu(std::atomic<int> &cache, K kernel)
+{
+    int n = cache.load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, WALK_BLOCK, 0) != hipSuccess || n < 1) n = 1;
+    cache.store(n, std::memory_order_relaxed);
+    return n;
+}
+
+int walk_resident_per_cu(int states)
+{
+    static std::atomic<int> c1{0}, c2{0}, c4{0}, ct{0};
+    switch (states) {
+    case 1: return resident_per_cu(c1, k_walk<1>);
+    case 2: return resident_per_cu(c2, k_walk<2>);
+    case 4: return resident_per_cu(c4, k_walk<4>);
+    default: return resident_per_cu(ct, k_tick);   // 0: the serving tick
+    }
 }
 
 hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st)

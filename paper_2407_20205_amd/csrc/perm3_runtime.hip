@@ -188,8 +188,13 @@ int32_t get_context(Context **out)
 
 bool timing_enabled() { return tl_timing; }
 
-int Context::waves_total() const { return cus * 4 * tuning.waves_per_simd; }
-int Context::grid_blocks() const { return cus * tuning.waves_per_simd; }
+// The persistent walk's workgroups (4 waves each, one per SIMD): waves_per_simd
+// per CU, but no more than fit on a CU at once.
+int Context::grid_blocks() const
+{
+    return cus * std::min(tuning.waves_per_simd, walk_resident_per_cu(tuning.states_per_lane));
+}
+int Context::waves_total() const { return 4 * grid_blocks(); }
 
 void Context::drop_graphs()
 {

@@ -276,7 +276,7 @@ int32_t perm_server::tick(std::vector<perm_done> &finished)
     ta.ntasks = d_counts;
     ta.tally = d_tally;
     ta.queue = d_counts + 2;
-    int blocks = cus * tuning.waves_per_simd;
+    int blocks = cus * std::min(tuning.waves_per_simd, walk_resident_per_cu(0));
     const int need = (int)((nt + 3) / 4);
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;

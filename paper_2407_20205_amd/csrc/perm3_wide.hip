@@ -19,6 +19,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <mutex>
 
 #include "perm3.h"
@@ -126,6 +127,16 @@ hipError_t launch_pack_wide(const uint8_t *A, int n, int vrows, RowX *rows, uint
     return hipGetLastError();
 }
 
+int wide_resident_per_cu()
+{
+    static std::atomic<int> cache{0};
+    int n = cache.load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_walk_wide, WALK_BLOCK, 0) != hipSuccess || n < 1) n = 1;
+    cache.store(n, std::memory_order_relaxed);
+    return n;
+}
+
 hipError_t launch_walk_wide(const WideArgs &a, int grid_blocks, hipStream_t st)
 {
     if (a.n < 1 || a.n > WIDE_MAX_N || a.m < 0 || a.m > 24) return hipErrorInvalidValue;
@@ -220,7 +231,8 @@ extern "C" int32_t perm_mod3_range_tally_wide(const uint8_t *A, int32_t n, uint6
     int64_t *h_tally = (int64_t *)(h + h_tally_at);
     memcpy(h, A, mat_bytes);
 
-    WideArgs a = plan_wide(c->tuning, c->waves_total(), n, begin, count);
+    const uint64_t resident = (uint64_t)c->cus * (uint64_t)std::min(c->tuning.waves_per_simd, wide_resident_per_cu());
+    WideArgs a = plan_wide(c->tuning, (int)(4 * resident), n, begin, count);
     a.rows = (const RowX *)(d + rows_at);
     a.tally = (int64_t *)(d + tally_at);
     a.queue = (uint64_t *)(d + queue_at);
@@ -237,7 +249,7 @@ extern "C" int32_t perm_mod3_range_tally_wide(const uint8_t *A, int32_t n, uint6
     WIDE_TRY(launch_pack_wide(d, n, std::min(varying, n), (RowX *)(d + rows_at), a.queue, a.tally, st));
     if (timed) WIDE_TRY(hipEventRecord(c->ev_walk0, st));
     const uint64_t want_blocks = (a.ntasks + 3) / 4;
-    const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(want_blocks, (uint64_t)c->grid_blocks()));
+    const int blocks = (int)std::max<uint64_t>(1, std::min<uint64_t>(want_blocks, resident));
     WIDE_TRY(launch_walk_wide(a, blocks, st));
     if (timed) WIDE_TRY(hipEventRecord(c->ev_walk1, st));
     WIDE_TRY(hipMemcpyAsync(h_tally, a.tally, sizeof(int64_t), hipMemcpyDeviceToHost, st));
