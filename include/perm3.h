@@ -284,7 +284,11 @@ typedef struct {
     int32_t states_per_lane;  /* chunks a lane walks side by side: 1, 2 or 4              */
     int32_t body_log_mid;     /* block log2 for direct_max_n < n <= mid_max_n: 4, 5 or 6  */
     int32_t mid_max_n;        /* see body_log_mid                                         */
-    int32_t reserved[3];
+    int32_t max_tasks_log;    /* a matrix is cut into at most 2^max_tasks_log tasks ...   */
+    int32_t min_task_log;     /* ... unless its tasks would then exceed 2^min_task_log Gray
+                                 indices; each task ends with an atomic on its matrix's
+                                 counters, and on one address those serialise (0..30)       */
+    int32_t reserved[1];
 } perm_tuning;
 
 int32_t perm_tuning_get(perm_tuning *t);

@@ -37,6 +37,8 @@ struct PlanArgs {
     int32_t body_log, chunk_log_max, direct_max_n, direct_chunk_log_max;
     int32_t body_log_mid, mid_max_n;  // block length for direct_max_n < n <= mid_max_n
     int32_t states_log;           // log2 of the chunks a lane carries side by side
+    int32_t max_tasks_log;        // at most 2^max_tasks_log tasks per matrix ...
+    int32_t min_task_log;         // ... unless tasks would exceed 2^min_task_log indices
     int32_t waves_total, tasks_per_wave;
     MatMeta *meta;
     int32_t *order;               // [count] matrix index by decreasing n

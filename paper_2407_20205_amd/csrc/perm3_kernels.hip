@@ -45,7 +45,10 @@ __device__ __forceinline__ int walk_lane(cptr<RowW> R, int n, int m, int mode, u
     const uint64_t a = a0 > lo ? a0 : lo;
     const uint64_t e = e0 < hi ? e0 : hi;
     if (a >= e) return 0;
-    if (mode == MODE_FAST && a == a0 && e == e0) return walk_chunks_fast<UL, 1>(R, n, m, c, mk, sr);
+    if (a == a0 && e == e0) {
+        if (mode == MODE_FAST) return walk_chunks_fast<UL, 1>(R, n, m, c, mk, sr);
+        return n > 32 ? walk_chunk_direct<true>(R, n, m, c, mk) : walk_chunk_direct<false>(R, n, m, c, mk);
+    }
     return n > 32 ? walk_range_direct<true>(R, n, a, e, mk) : walk_range_direct<false>(R, n, a, e, mk);
 }
 
@@ -193,7 +196,13 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
                 // a lane's int32 tally covers S chunks and a wave sums 64 lanes: S * 2^m <= 2^24
                 int mmax = a.chunk_log_max < n - 6 - slog ? a.chunk_log_max : n - 6 - slog;
                 if (mmax > 24 - slog) mmax = 24 - slog;
-                m = target_m;
+                // at most 2^max_tasks_log tasks for this matrix, unless its tasks
+                // would then exceed 2^min_task_log indices: every task ends with an
+                // atomic on the matrix's counters, and those serialise
+                const int fewer = n - 6 - slog - a.max_tasks_log;
+                const int longest = a.min_task_log - 6 - slog;
+                const int mfloor = fewer < longest ? fewer : longest;
+                m = target_m > mfloor ? target_m : mfloor;
                 if (m > mmax) m = mmax;
                 if (m < ul + 1) m = ul + 1;
                 mt.mode = MODE_FAST;

@@ -66,11 +66,13 @@ perm_tuning default_tuning()
     t.body_log = 5;
     t.chunk_log_max = 20;
     t.tasks_per_wave = 16;
-    t.direct_max_n = 16;
+    t.direct_max_n = 11;
     t.use_graphs = 1;
     t.states_per_lane = 1;
     t.body_log_mid = 4;
     t.mid_max_n = 31;
+    t.max_tasks_log = 10;
+    t.min_task_log = 19;
     return t;
 }
 
@@ -82,7 +84,8 @@ bool tuning_valid(const perm_tuning &t)
            (t.use_graphs == 0 || t.use_graphs == 1) &&
            (t.states_per_lane == 1 || t.states_per_lane == 2 || t.states_per_lane == 4) &&
            t.body_log_mid >= 4 && t.body_log_mid <= 6 && t.mid_max_n >= 0 && t.mid_max_n <= 63 &&
-           t.direct_max_n >= t.body_log_mid + 6;
+           t.direct_max_n >= t.body_log_mid + 6 && t.min_task_log >= 0 && t.min_task_log <= 30 &&
+           t.max_tasks_log >= 0 && t.max_tasks_log <= 40;
 }
 
 // ------------------------------------------------------------------ context
@@ -247,6 +250,8 @@ PlanArgs Context::plan_args(const int32_t *ns_dev, int32_t count, uint8_t *out_d
     a.body_log_mid = tuning.body_log_mid;
     a.mid_max_n = tuning.mid_max_n;
     a.states_log = tuning.states_per_lane == 4 ? 2 : (tuning.states_per_lane == 2 ? 1 : 0);
+    a.max_tasks_log = tuning.max_tasks_log;
+    a.min_task_log = tuning.min_task_log;
     a.waves_total = waves_total();
     a.tasks_per_wave = tuning.tasks_per_wave;
     a.meta = (MatMeta *)meta.p;

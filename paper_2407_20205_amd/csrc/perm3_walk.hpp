@@ -27,6 +27,11 @@
 #ifndef PERM3_BITOP3
 #define PERM3_BITOP3(a, b, c, tt) __builtin_amdgcn_bitop3_b32((a), (b), (c), (tt))
 #endif
+// A value every active lane of the wave holds alike, made a scalar so that
+// the row it indexes is read with scalar loads.
+#ifndef PERM3_UNIFORM
+#define PERM3_UNIFORM(x) __builtin_amdgcn_readfirstlane(x)
+#endif
 
 namespace perm3 {
 
@@ -201,15 +206,21 @@ PERM3_FN int rewalk_exact(RP R, int n, I ia, I ib, uint32_t ml, uint32_t sl, con
 // undone step may leave a zero as (0,1) where the forward walk had (0,0); the
 // test reads only mag and, where every mag bit is set, sgn, and neither
 // depends on how a zero is represented.
+//
+// All lanes of a wave walk their chunks in step, so within a block every
+// active lane is at the same offset: the flipped row and its direction (a
+// block never contains the chunk's middle step, the only one whose direction
+// differs between lanes) are wave-uniform and the rows come in by scalar
+// loads.
 template <typename RP, typename I, typename MK>
 PERM3_FN int rewalk_back(RP R, int n, I ia, I ib, uint32_t ml, uint32_t sl, const MK &mk)
 {
     int tally = 0;
     for (I i = ib; i != ia; --i) {
         tally += exact_term(R, n, i, ml, sl, mk);
-        const uint64_t il = (uint64_t)i;
-        const int t = __builtin_ctzll(il);
-        const bool left = (il >> (t + 1)) & 1u;   // the step into i removed row t
+        const uint32_t il = (uint32_t)i;                 // offsets within a chunk fit 32 bits
+        const int t = PERM3_UNIFORM(__builtin_ctz(il));
+        const bool left = PERM3_UNIFORM((il >> (t + 1)) & 1u);   // the step into i removed row t
         bip_add(ml, sl, R[t].m_lo, left ? R[t].s_lo : R[t].sn_lo);
     }
     return tally;
@@ -359,8 +370,45 @@ PERM3_FN int walk_lane_wide(RP R, int n, int m, bool fast, u128 c0, uint64_t off
     return exact_term(R, n, ia, ml, sl, mk) + rewalk_exact(R, n, ia, base + (oe - 1), ml, sl, mk);
 }
 
+// Exact walk of the whole aligned chunk c of length 2^m, both words carried
+// and every index tested (small matrices).  The offset j within the chunk is
+// the loop counter, the same in every lane walking a whole chunk, so the
+// flipped row t = ctz(j) is wave-uniform and read with scalar loads; only the
+// middle step (t = m-1, whose direction is the chunk index's parity) selects
+// the row's sign word per lane.
+template <bool HI, typename RP>
+PERM3_FN int walk_chunk_direct(RP R, int n, int m, uint64_t c, Masks mk)
+{
+    const uint64_t a = c << m;
+    const uint64_t g = a ^ (a >> 1);
+    uint32_t ml = 0, sl = 0, mh = 0, sh = 0;
+    for (int k = 0; k < n; ++k) {
+        const uint32_t sel = 0u - (uint32_t)((g >> k) & 1u);
+        bip_add(ml, sl, R[k].m_lo & sel, R[k].s_lo & sel);
+        if (HI) bip_add(mh, sh, R[k].m_hi & sel, R[k].s_hi & sel);
+    }
+    int tally = 0;
+    if (ml == mk.lo && (!HI || mh == mk.hi)) {
+        const int par = (__builtin_popcount(sl & mk.lo) + (HI ? __builtin_popcount(sh & mk.hi) : 0) + (int)(a & 1u)) & 1;
+        tally += par ? -1 : 1;
+    }
+    const bool odd = (c & 1u) != 0;
+    const uint32_t len = 1u << m;
+    for (uint32_t j = 1; j < len; ++j) {
+        const int t = __builtin_ctz(j);
+        const bool leave = t + 1 < m ? ((j >> (t + 1)) & 1u) != 0 : odd;
+        bip_add(ml, sl, R[t].m_lo, leave ? R[t].sn_lo : R[t].s_lo);
+        if (HI) bip_add(mh, sh, R[t].m_hi, leave ? R[t].sn_hi : R[t].s_hi);
+        if (ml == mk.lo && (!HI || mh == mk.hi)) {
+            const int par = (__builtin_popcount(sl & mk.lo) + (HI ? __builtin_popcount(sh & mk.hi) : 0) + (int)(j & 1u)) & 1;
+            tally += par ? -1 : 1;
+        }
+    }
+    return tally;
+}
+
 // Exact walk of an arbitrary range [a, e) with both words carried and every
-// index tested: small matrices, ragged ends of a range, and checks.
+// index tested: ragged ends of a range, and checks.
 template <bool HI, typename RP>
 PERM3_FN int walk_range_direct(RP R, int n, uint64_t a, uint64_t e, Masks mk)
 {

@@ -161,7 +161,11 @@ WideArgs plan_wide(const perm_tuning &tn, int waves_total, int n, u128 begin, ui
         int target = 0;
         if (per_task >= 128.0) target = (63 - __builtin_clzll((uint64_t)per_task)) - 6;
         const int mmax = std::min(std::min(tn.chunk_log_max, n - 6), 24);
-        m = std::max(std::min(target, mmax), a.ul + 1);
+        // at most 2^max_tasks_log tasks unless they would exceed 2^min_task_log indices
+        const int count_log = count > 1 ? 64 - __builtin_clzll(count - 1) : 0;   // ceil(log2 count)
+        const int fewer = count_log - 6 - tn.max_tasks_log;
+        const int mfloor = std::min(fewer, tn.min_task_log - 6);
+        m = std::max(std::min(std::max(target, mfloor), mmax), a.ul + 1);
         a.mode = MODE_FAST;
     } else {
         m = std::max(std::min(n - 6, 10), 0);
