@@ -119,6 +119,8 @@ struct FinishArgs {
 };
 
 hipError_t launch_plan(const PlanArgs &a, hipStream_t st);
+constexpr int SMALL_PLAN_MAX = 64;   // calls of up to this many matrices plan (and pack) in one wave
+hipError_t launch_plan_small(const PlanArgs &a, const PackU8Args &pk, bool pack, hipStream_t st);
 hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st);
 hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st);
 hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st);

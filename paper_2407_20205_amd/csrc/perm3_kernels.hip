@@ -104,6 +104,93 @@ __device__ __forceinline__ void range_of(const PlanArgs &a, int n, uint64_t &lo,
     }
 }
 
+// Chunk log that gives each persistent wave about tasks_per_wave tasks of the
+// whole call's work.
+__device__ __forceinline__ int target_chunk_log(const PlanArgs &a, double total_work)
+{
+    const double want_tasks = (double)a.waves_total * (double)(a.tasks_per_wave > 0 ? a.tasks_per_wave : 1);
+    const double per_task = total_work / want_tasks;
+    if (per_task < 128.0) return 0;
+    return (63 - __builtin_clzll((uint64_t)per_task)) - 6 - a.states_log;
+}
+
+// The plan of matrix k: its mode, chunk log, block log, Gray range and task
+// count (row_base is filled in later).  Clears the matrix's tally, completion
+// count and status, and writes the result of matrices that need no walk.
+__device__ MatMeta plan_matrix(const PlanArgs &a, int k, int target_m)
+{
+    const int n = a.ns[k];
+    const bool valid = n >= 0 && n <= 63;
+    MatMeta mt;
+    mt.n = valid ? n : 0;
+    mt.m = 0;
+    mt.mode = MODE_NONE;
+    mt.ntasks = 0;
+    mt.row_base = 0;
+    mt.lo = 0;
+    mt.hi = 0;
+    mt.c_first = 0;
+    mt.ul = a.body_log;
+    a.tally[k] = 0;
+    a.done[k] = 0;
+    a.status[k] = valid ? 0 : 1;
+    if (!valid) {
+        a.out[k] = 0xFF;
+    } else if (n == 0) {
+        // the one subset (Gray index 0) is empty: its empty product makes
+        // a term of +1, and perm of the 0 x 0 matrix is 1
+        uint64_t lo, hi;
+        range_of(a, 0, lo, hi);
+        const long long T = lo < hi ? 1 : 0;
+        a.tally[k] = T;
+        const uint8_t r = finish_mod3(0, T);
+        a.out[k] = r;
+        if (a.hist) atomicAdd((unsigned long long *)&a.hist[r], 1ull);
+    } else {
+        uint64_t lo, hi;
+        range_of(a, n, lo, hi);
+        mt.lo = lo;
+        mt.hi = hi;
+        const int slog = a.states_log;
+        const int ul = n <= a.mid_max_n ? a.body_log_mid : a.body_log;
+        mt.ul = ul;
+        const bool fast_ok = n >= ul + 7 + slog && n > a.direct_max_n;
+        int m;
+        if (fast_ok) {
+            // a lane's int32 tally covers S chunks and a wave sums 64 lanes: S * 2^m <= 2^24
+            int mmax = a.chunk_log_max < n - 6 - slog ? a.chunk_log_max : n - 6 - slog;
+            if (mmax > 24 - slog) mmax = 24 - slog;
+            // at most 2^max_tasks_log tasks for this matrix, unless its tasks
+            // would then exceed 2^min_task_log indices: every task ends with an
+            // atomic on the matrix's counters, and those serialise
+            const int fewer = n - 6 - slog - a.max_tasks_log;
+            const int longest = a.min_task_log - 6 - slog;
+            const int mfloor = fewer < longest ? fewer : longest;
+            m = target_m > mfloor ? target_m : mfloor;
+            if (m > mmax) m = mmax;
+            if (m < ul + 1) m = ul + 1;
+            mt.mode = MODE_FAST;
+        } else {
+            m = n - 6;
+            if (m > a.direct_chunk_log_max) m = a.direct_chunk_log_max;
+            if (m < 0) m = 0;
+            mt.mode = MODE_DIRECT;
+        }
+        mt.m = m;
+        if (hi > lo) {
+            const uint64_t c0 = lo >> m;
+            const uint64_t c1 = (hi - 1) >> m;
+            mt.c_first = c0;
+            const uint64_t per_task = 64ull << a.states_log;
+            mt.ntasks = (c1 - c0 + per_task) / per_task;
+        } else {
+            mt.mode = MODE_NONE;
+            a.out[k] = finish_mod3(n, 0);
+        }
+    }
+    return mt;
+}
+
 __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
 {
     __shared__ double s_dbl[1024];
@@ -145,86 +232,12 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
     }
     __syncthreads();
 
-    // chunk length that gives each persistent wave about tasks_per_wave tasks
-    const double want_tasks = (double)a.waves_total * (double)(a.tasks_per_wave > 0 ? a.tasks_per_wave : 1);
-    const double per_task = total_work / want_tasks;
-    int target_m = 0;
-    if (per_task >= 128.0) {
-        const uint64_t pt = (uint64_t)per_task;
-        target_m = (63 - __builtin_clzll(pt)) - 6 - a.states_log;
-    }
-
+    const int target_m = target_chunk_log(a, total_work);
     for (int k = tid; k < a.count; k += 1024) {
+        const MatMeta mt = plan_matrix(a, k, target_m);
+        a.meta[k] = mt;
         const int n = a.ns[k];
         const bool valid = n >= 0 && n <= 63;
-        MatMeta mt;
-        mt.n = valid ? n : 0;
-        mt.m = 0;
-        mt.mode = MODE_NONE;
-        mt.ntasks = 0;
-        mt.row_base = 0;
-        mt.lo = 0;
-        mt.hi = 0;
-        mt.c_first = 0;
-        mt.ul = a.body_log;
-        a.tally[k] = 0;
-        a.done[k] = 0;
-        a.status[k] = valid ? 0 : 1;
-        if (!valid) {
-            a.out[k] = 0xFF;
-        } else if (n == 0) {
-            // the one subset (Gray index 0) is empty: its empty product makes
-            // a term of +1, and perm of the 0 x 0 matrix is 1
-            uint64_t lo, hi;
-            range_of(a, 0, lo, hi);
-            const long long T = lo < hi ? 1 : 0;
-            a.tally[k] = T;
-            const uint8_t r = finish_mod3(0, T);
-            a.out[k] = r;
-            if (a.hist) atomicAdd((unsigned long long *)&a.hist[r], 1ull);
-        } else {
-            uint64_t lo, hi;
-            range_of(a, n, lo, hi);
-            mt.lo = lo;
-            mt.hi = hi;
-            const int slog = a.states_log;
-            const int ul = n <= a.mid_max_n ? a.body_log_mid : a.body_log;
-            mt.ul = ul;
-            const bool fast_ok = n >= ul + 7 + slog && n > a.direct_max_n;
-            int m;
-            if (fast_ok) {
-                // a lane's int32 tally covers S chunks and a wave sums 64 lanes: S * 2^m <= 2^24
-                int mmax = a.chunk_log_max < n - 6 - slog ? a.chunk_log_max : n - 6 - slog;
-                if (mmax > 24 - slog) mmax = 24 - slog;
-                // at most 2^max_tasks_log tasks for this matrix, unless its tasks
-                // would then exceed 2^min_task_log indices: every task ends with an
-                // atomic on the matrix's counters, and those serialise
-                const int fewer = n - 6 - slog - a.max_tasks_log;
-                const int longest = a.min_task_log - 6 - slog;
-                const int mfloor = fewer < longest ? fewer : longest;
-                m = target_m > mfloor ? target_m : mfloor;
-                if (m > mmax) m = mmax;
-                if (m < ul + 1) m = ul + 1;
-                mt.mode = MODE_FAST;
-            } else {
-                m = n - 6;
-                if (m > a.direct_chunk_log_max) m = a.direct_chunk_log_max;
-                if (m < 0) m = 0;
-                mt.mode = MODE_DIRECT;
-            }
-            mt.m = m;
-            if (hi > lo) {
-                const uint64_t c0 = lo >> m;
-                const uint64_t c1 = (hi - 1) >> m;
-                mt.c_first = c0;
-                const uint64_t per_task = 64ull << a.states_log;
-                mt.ntasks = (c1 - c0 + per_task) / per_task;
-            } else {
-                mt.mode = MODE_NONE;
-                a.out[k] = finish_mod3(n, 0);
-            }
-        }
-        a.meta[k] = mt;
         const uint32_t pos = atomicAdd(&s_cursor[valid ? n : 64], 1u);
         a.order[pos] = k;
     }
@@ -314,6 +327,85 @@ __global__ void __launch_bounds__(64) k_pack_planes(PackPlanesArgs a)
     const uint64_t high = (n >= 64) ? 0 : ~((1ull << n) - 1ull);
     if ((mag | sgn) & high) a.status[k] = 1;
     store_row(a.rows + mt.row_base + r, mag, sgn);
+}
+
+// ------------------------------------------------------------------ small calls
+
+// Up to SMALL_PLAN_MAX matrices planned by one wavefront (each lane takes its
+// rank in the task order and its prefix sums over the other lanes, no block
+// scans) and, for byte matrices, packed in the same launch: a single matrix
+// costs one short kernel before the walk instead of two.
+__global__ void __launch_bounds__(64) k_plan_small(PlanArgs a, PackU8Args pk, int pack)
+{
+    __shared__ double s_w[64];
+    __shared__ int s_key[64];
+    __shared__ uint64_t s_ntasks[64];
+    __shared__ int s_n[64];
+    __shared__ int s_mode[64];
+    __shared__ int64_t s_row_base[64];
+    const int k = threadIdx.x;
+    const bool have = k < a.count;
+    const int n = have ? a.ns[k] : -1;
+    const bool valid = have && n >= 0 && n <= 63;
+    double w = 0.0;
+    if (valid) {
+        uint64_t lo, hi;
+        range_of(a, n, lo, hi);
+        w = (double)(hi - lo);
+    }
+    s_w[k] = w;
+    s_key[k] = have ? (valid ? n : -1) : -2;   // larger n first, then invalid n, then unused lanes
+    if (k == 0) a.counters[CNT_QUEUE] = 0;
+    __syncthreads();
+    double total_work = 0.0;
+    for (int j = 0; j < 64; ++j) total_work += s_w[j];
+    const int target_m = target_chunk_log(a, total_work);
+    MatMeta mt;
+    if (have) mt = plan_matrix(a, k, target_m);
+    s_ntasks[k] = have ? mt.ntasks : 0;
+    s_n[k] = have ? mt.n : 0;
+    s_mode[k] = have ? mt.mode : (int)MODE_NONE;
+    __syncthreads();
+    int rank = 0;
+    uint64_t first = 0, total_tasks = 0;
+    int64_t row_base = 0;
+    for (int j = 0; j < 64; ++j) {
+        const bool before = s_key[j] > s_key[k] || (s_key[j] == s_key[k] && j < k);
+        rank += before ? 1 : 0;
+        if (before) first += s_ntasks[j];
+        total_tasks += s_ntasks[j];
+        if (j < k) row_base += s_n[j];
+    }
+    s_row_base[k] = row_base;
+    if (have) {
+        mt.row_base = row_base;
+        a.meta[k] = mt;
+        a.order[rank] = k;
+        a.task_start[rank] = first;
+    }
+    if (k == 0) {
+        a.task_start[a.count] = total_tasks;
+        a.counters[CNT_TOTAL_TASKS] = total_tasks;
+    }
+    if (!pack) return;
+    __syncthreads();
+    // phi (Section 2) of every byte matrix, one row per lane, with validation
+    for (int j = 0; j < a.count; ++j) {
+        const int nj = s_n[j];
+        if (s_mode[j] == MODE_NONE || k >= nj) continue;
+        const uint8_t *row = pk.mats + pk.offs[j] + (int64_t)k * nj;
+        uint64_t mag = 0, sgn = 0;
+        bool bad = false;
+        for (int c = 0; c < nj; ++c) {
+            const uint8_t v = row[c];
+            const uint64_t bit = 1ull << (nj - 1 - c);
+            bad |= v > 2;
+            if (v != 0) mag |= bit;
+            if (v == 2) sgn |= bit;
+        }
+        if (bad) pk.status[j] = 1;
+        store_row(pk.rows + s_row_base[j] + k, mag, sgn);
+    }
 }
 
 // ------------------------------------------------------------------ walk
@@ -471,6 +563,13 @@ __global__ void k_bipedal_ops(const uint32_t *in, int count, uint32_t *out)
 hipError_t launch_plan(const PlanArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_small(const PlanArgs &a, const PackU8Args &pk, bool pack, hipStream_t st)
+{
+    if (a.count < 1 || a.count > SMALL_PLAN_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(64), 0, st, a, pk, pack ? 1 : 0);
     return hipGetLastError();
 }
 

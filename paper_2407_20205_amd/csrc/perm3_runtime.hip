@@ -291,16 +291,20 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
     pa.range_lo = L.range_lo;
     pa.range_hi = L.range_hi;
     if (timed) HIP_TRY(hipEventRecord(ev_all0, st));
-    HIP_TRY(launch_plan(pa, st));
+    PackU8Args pk;
+    pk.mats = L.mats_dev;
+    pk.offs = L.offs_dev;
+    pk.meta = (const MatMeta *)meta.p;
+    pk.count = L.count;
+    pk.rows = (RowW *)rowbuf.p;
+    pk.status = (uint8_t *)status.p;
+    const bool small = L.count <= SMALL_PLAN_MAX;
+    if (small)
+        HIP_TRY(launch_plan_small(pa, pk, L.pack_kind == 0, st));   // byte matrices packed in the same launch
+    else
+        HIP_TRY(launch_plan(pa, st));
     if (L.pack_kind == 0) {
-        PackU8Args pk;
-        pk.mats = L.mats_dev;
-        pk.offs = L.offs_dev;
-        pk.meta = (const MatMeta *)meta.p;
-        pk.count = L.count;
-        pk.rows = (RowW *)rowbuf.p;
-        pk.status = (uint8_t *)status.p;
-        HIP_TRY(launch_pack_u8(pk, st));
+        if (!small) HIP_TRY(launch_pack_u8(pk, st));
     } else {
         PackPlanesArgs pk;
         pk.planes = L.planes_dev;
@@ -318,7 +322,7 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
         HIP_TRY(hipEventRecord(ev_all1, st));
     }
     last_timing_valid = timed;
-    last_launches = 3;
+    last_launches = small && L.pack_kind == 0 ? 2 : 3;
     return PERM_OK;
 }
 
@@ -365,7 +369,7 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
     }
     HIP_TRY(hipGraphLaunch(it->second, st));
     last_timing_valid = false;
-    last_launches = 3;
+    last_launches = L.count <= SMALL_PLAN_MAX && L.pack_kind == 0 ? 2 : 3;
     return mark(st);
 }
 
