@@ -115,9 +115,11 @@ __device__ __forceinline__ int target_chunk_log(const PlanArgs &a, double total_
 }
 
 // The plan of matrix k: its mode, chunk log, block log, Gray range and task
-// count (row_base is filled in later).  Clears the matrix's tally, completion
-// count and status, and writes the result of matrices that need no walk.
-__device__ MatMeta plan_matrix(const PlanArgs &a, int k, int target_m)
+// count (row_base is filled in later).  Clears the matrix's tally and
+// completion count, sets its status (always for an invalid order, otherwise
+// only with write_status: a packer running beside the plan owns it then), and
+// writes the result of matrices that need no walk.
+__device__ MatMeta plan_matrix(const PlanArgs &a, int k, int target_m, bool write_status)
 {
     const int n = a.ns[k];
     const bool valid = n >= 0 && n <= 63;
@@ -133,7 +135,7 @@ __device__ MatMeta plan_matrix(const PlanArgs &a, int k, int target_m)
     mt.ul = a.body_log;
     a.tally[k] = 0;
     a.done[k] = 0;
-    a.status[k] = valid ? 0 : 1;
+    if (write_status || !valid) a.status[k] = valid ? 0 : 1;
     if (!valid) {
         a.out[k] = 0xFF;
     } else if (n == 0) {
@@ -234,7 +236,7 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
 
     const int target_m = target_chunk_log(a, total_work);
     for (int k = tid; k < a.count; k += 1024) {
-        const MatMeta mt = plan_matrix(a, k, target_m);
+        const MatMeta mt = plan_matrix(a, k, target_m, true);
         a.meta[k] = mt;
         const int n = a.ns[k];
         const bool valid = n >= 0 && n <= 63;
@@ -331,20 +333,25 @@ __global__ void __launch_bounds__(64) k_pack_planes(PackPlanesArgs a)
 
 // ------------------------------------------------------------------ small calls
 
-// Up to SMALL_PLAN_MAX matrices planned by one wavefront (each lane takes its
-// rank in the task order and its prefix sums over the other lanes, no block
-// scans) and, for byte matrices, packed in the same launch: a single matrix
-// costs one short kernel before the walk instead of two.
-__global__ void __launch_bounds__(64) k_plan_small(PlanArgs a, PackU8Args pk, int pack)
+constexpr int SMALL_BLOCK = 256;
+
+// Lane j's value of a 64-bit variable, read by every lane (j wave-uniform).
+__device__ __forceinline__ uint64_t readlane64(uint64_t v, int j)
 {
-    __shared__ double s_w[64];
-    __shared__ int s_key[64];
-    __shared__ uint64_t s_ntasks[64];
-    __shared__ int s_n[64];
-    __shared__ int s_mode[64];
-    __shared__ int64_t s_row_base[64];
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, j);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), j);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Planning of up to SMALL_PLAN_MAX matrices by one wavefront: lane k plans
+// matrix k and takes its rank in the task order and its prefix sums from the
+// other lanes' registers (readlane over the call's matrices only), with no
+// LDS round trips and no block scans.
+__device__ void plan_small(const PlanArgs &a, bool write_status)
+{
     const int k = threadIdx.x;
-    const bool have = k < a.count;
+    const int count = a.count;
+    const bool have = k < count;
     const int n = have ? a.ns[k] : -1;
     const bool valid = have && n >= 0 && n <= 63;
     double w = 0.0;
@@ -353,30 +360,27 @@ __global__ void __launch_bounds__(64) k_plan_small(PlanArgs a, PackU8Args pk, in
         range_of(a, n, lo, hi);
         w = (double)(hi - lo);
     }
-    s_w[k] = w;
-    s_key[k] = have ? (valid ? n : -1) : -2;   // larger n first, then invalid n, then unused lanes
+    const int key = have ? (valid ? n : -1) : -2;   // larger n first, then invalid n
     if (k == 0) a.counters[CNT_QUEUE] = 0;
-    __syncthreads();
     double total_work = 0.0;
-    for (int j = 0; j < 64; ++j) total_work += s_w[j];
+    for (int j = 0; j < count; ++j) total_work += __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(w), j));
     const int target_m = target_chunk_log(a, total_work);
     MatMeta mt;
-    if (have) mt = plan_matrix(a, k, target_m);
-    s_ntasks[k] = have ? mt.ntasks : 0;
-    s_n[k] = have ? mt.n : 0;
-    s_mode[k] = have ? mt.mode : (int)MODE_NONE;
-    __syncthreads();
+    if (have) mt = plan_matrix(a, k, target_m, write_status);
+    const uint64_t ntasks = have ? mt.ntasks : 0;
+    const int rows = have ? mt.n : 0;
     int rank = 0;
     uint64_t first = 0, total_tasks = 0;
     int64_t row_base = 0;
-    for (int j = 0; j < 64; ++j) {
-        const bool before = s_key[j] > s_key[k] || (s_key[j] == s_key[k] && j < k);
+    for (int j = 0; j < count; ++j) {
+        const int kj = __builtin_amdgcn_readlane(key, j);
+        const uint64_t tj = readlane64(ntasks, j);
+        const bool before = kj > key || (kj == key && j < k);
         rank += before ? 1 : 0;
-        if (before) first += s_ntasks[j];
-        total_tasks += s_ntasks[j];
-        if (j < k) row_base += s_n[j];
+        if (before) first += tj;
+        total_tasks += tj;
+        if (j < k) row_base += __builtin_amdgcn_readlane(rows, j);
     }
-    s_row_base[k] = row_base;
     if (have) {
         mt.row_base = row_base;
         a.meta[k] = mt;
@@ -384,27 +388,68 @@ __global__ void __launch_bounds__(64) k_plan_small(PlanArgs a, PackU8Args pk, in
         a.task_start[rank] = first;
     }
     if (k == 0) {
-        a.task_start[a.count] = total_tasks;
+        a.task_start[count] = total_tasks;
         a.counters[CNT_TOTAL_TASKS] = total_tasks;
     }
-    if (!pack) return;
+}
+
+// phi (Section 2) of byte matrix j with its validation: the matrix (at most
+// 63 x 63 bytes) is read once with coalesced byte loads, all in flight
+// together, into LDS, and lane r forms row r from there.  Its first row is
+// the sum of the earlier matrices' orders (invalid orders count 0, as in the
+// plan).  This block alone writes the matrix's status when its order is valid.
+__device__ void pack_small(const PlanArgs &a, const PackU8Args &pk, int j)
+{
+    __shared__ uint8_t s_mat[SMALL_BLOCK * 16];
+    __shared__ long long s_base;
+    const int t = threadIdx.x;
+    const int n = a.ns[j];
+    if (n < 0 || n > 63) return;                  // the plan marks it invalid
+    if (n == 0) {
+        if (t == 0) pk.status[j] = 0;
+        return;
+    }
+    if (t < 64) {
+        const int ni = t < j ? a.ns[t] : 0;
+        const long long base = wave_sum_i64(ni >= 0 && ni <= 63 ? ni : 0);
+        if (t == 0) s_base = base;
+    }
+    const int nn = n * n;
+    const uint8_t *src = pk.mats + pk.offs[j];
+    uint8_t v[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int idx = t + SMALL_BLOCK * i;
+        v[i] = idx < nn ? src[idx] : 0;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) s_mat[t + SMALL_BLOCK * i] = v[i];
     __syncthreads();
-    // phi (Section 2) of every byte matrix, one row per lane, with validation
-    for (int j = 0; j < a.count; ++j) {
-        const int nj = s_n[j];
-        if (s_mode[j] == MODE_NONE || k >= nj) continue;
-        const uint8_t *row = pk.mats + pk.offs[j] + (int64_t)k * nj;
-        uint64_t mag = 0, sgn = 0;
-        bool bad = false;
-        for (int c = 0; c < nj; ++c) {
-            const uint8_t v = row[c];
-            const uint64_t bit = 1ull << (nj - 1 - c);
-            bad |= v > 2;
-            if (v != 0) mag |= bit;
-            if (v == 2) sgn |= bit;
-        }
-        if (bad) pk.status[j] = 1;
-        store_row(pk.rows + s_row_base[j] + k, mag, sgn);
+    if (t >= n) return;
+    const uint8_t *row = s_mat + t * n;
+    uint64_t mag = 0, sgn = 0;
+    bool bad = false;
+    for (int c = 0; c < n; ++c) {
+        const uint8_t x = row[c];
+        const uint64_t bit = 1ull << (n - 1 - c);
+        bad |= x > 2;
+        if (x != 0) mag |= bit;
+        if (x == 2) sgn |= bit;
+    }
+    bad = __any(bad);
+    if (t == 0) pk.status[j] = bad ? 1 : 0;
+    store_row(pk.rows + s_base + t, mag, sgn);
+}
+
+// A call of up to SMALL_PLAN_MAX matrices: block 0 plans; for byte matrices,
+// block 1 + j packs matrix j in the same launch (no dependence on the plan).
+__global__ void __launch_bounds__(SMALL_BLOCK) k_plan_small(PlanArgs a, PackU8Args pk, int pack)
+{
+    if (blockIdx.x == 0) {
+        if (threadIdx.x >= 64) return;
+        plan_small(a, pack == 0);
+    } else {
+        pack_small(a, pk, blockIdx.x - 1);
     }
 }
 
@@ -569,7 +614,7 @@ hipError_t launch_plan(const PlanArgs &a, hipStream_t st)
 hipError_t launch_plan_small(const PlanArgs &a, const PackU8Args &pk, bool pack, hipStream_t st)
 {
     if (a.count < 1 || a.count > SMALL_PLAN_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_plan_small, dim3(1), dim3(64), 0, st, a, pk, pack ? 1 : 0);
+    hipLaunchKernelGGL(k_plan_small, dim3(1 + (pack ? a.count : 0)), dim3(SMALL_BLOCK), 0, st, a, pk, pack ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -72,7 +72,8 @@ struct Context {
     std::map<GraphKey, hipGraphExec_t> graphs;
     hipEvent_t ev_walk0 = nullptr, ev_walk1 = nullptr, ev_all0 = nullptr, ev_all1 = nullptr;
     hipEvent_t ev_done = nullptr, ev_in = nullptr, ev_out = nullptr;
-    hipStream_t last_stream = nullptr;
+    hipStream_t last_stream = nullptr;   // stream of the last call (valid when have_last)
+    bool have_last = false;
     bool last_timing_valid = false;
     int last_launches = 0;
     int last_graph = 0;

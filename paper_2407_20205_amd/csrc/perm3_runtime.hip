@@ -226,7 +226,7 @@ int32_t Context::reserve_work(int32_t count, int64_t rows)
 // Order this call after every earlier call of the context (they share buffers).
 int32_t Context::join(hipStream_t st)
 {
-    if (last_stream && last_stream != st) HIP_TRY(hipStreamWaitEvent(st, ev_done, 0));
+    if (have_last && last_stream != st) HIP_TRY(hipStreamWaitEvent(st, ev_done, 0));
     return PERM_OK;
 }
 
@@ -234,6 +234,7 @@ int32_t Context::mark(hipStream_t st)
 {
     HIP_TRY(hipEventRecord(ev_done, st));
     last_stream = st;
+    have_last = true;
     return PERM_OK;
 }
 
@@ -333,7 +334,9 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
     int32_t rc = join(st);
     if (rc) return rc;
     last_graph = 0;
-    if (timed || !use_graph || !tuning.use_graphs) {
+    // Calls of up to SMALL_PLAN_MAX matrices are two launches, issued directly:
+    // replaying them as a graph costs more than it saves.
+    if (timed || !use_graph || !tuning.use_graphs || L.count <= SMALL_PLAN_MAX) {
         rc = enqueue(L, st, timed);
         if (rc) return rc;
         return mark(st);
@@ -373,12 +376,16 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
     return mark(st);
 }
 
-// A device-input call on the caller's stream, or, for a NULL stream, on the
-// library's stream ordered after earlier and before later work on the legacy
-// default stream (where torch runs unless told otherwise).
+// A device-input call on the caller's stream.  For a NULL stream (where torch
+// runs unless told otherwise): a call launched directly goes on the NULL
+// stream itself; a graph, which cannot be captured there, is replayed on the
+// library's stream, ordered after earlier and before later work on the NULL
+// stream.
 int32_t Context::run_dev(const Launch &L, hipStream_t user)
 {
     if (user) return run(L, user, true);
+    // a call launched directly (no graph capture) goes on the NULL stream itself
+    if (L.count <= SMALL_PLAN_MAX || !tuning.use_graphs) return run(L, nullptr, false);
     HIP_TRY(hipEventRecord(ev_in, nullptr));
     HIP_TRY(hipStreamWaitEvent(stream, ev_in, 0));
     int32_t rc = run(L, stream, true);
