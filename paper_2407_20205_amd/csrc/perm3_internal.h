@@ -119,8 +119,16 @@ struct FinishArgs {
 };
 
 hipError_t launch_plan(const PlanArgs &a, hipStream_t st);
-constexpr int SMALL_PLAN_MAX = 64;   // calls of up to this many matrices plan (and pack) in one wave
-hipError_t launch_plan_small(const PlanArgs &a, const PackU8Args &pk, bool pack, hipStream_t st);
+constexpr int SMALL_PLAN_MAX = 64;   // calls of up to this many matrices are planned (and packed) by k_small
+constexpr uint64_t SMALL_FUSED_WORK = 1ull << 28;   // ... and are walked in the same launch up to this many indices
+
+// Per-matrix accumulators of one-launch small calls: zero between calls.
+struct SmallAcc {
+    int64_t *tally;     // SMALL_PLAN_MAX entries
+    uint64_t *done;     // SMALL_PLAN_MAX entries
+};
+hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const SmallAcc &acc, bool pack, bool allow_fused,
+                        int states, int blocks, hipStream_t st);
 hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st);
 hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st);
 hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st);

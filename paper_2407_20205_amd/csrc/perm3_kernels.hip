@@ -35,8 +35,8 @@ __device__ __forceinline__ Masks masks_for(int n)
 }
 
 // Walk one lane's chunk c (chunk length 2^m) clipped to [lo, hi).
-template <int UL>
-__device__ __forceinline__ int walk_lane(cptr<RowW> R, int n, int m, int mode, uint64_t c,
+template <int UL, typename RP>
+__device__ __forceinline__ int walk_lane(RP R, int n, int m, int mode, uint64_t c,
                                          uint64_t lo, uint64_t hi, const StaticRows<UL> &sr)
 {
     const Masks mk = masks_for(n);
@@ -54,8 +54,8 @@ __device__ __forceinline__ int walk_lane(cptr<RowW> R, int n, int m, int mode, u
 
 // Walk a lane's S chunks c + 64 s, s = 0 .. S-1, clipped to [lo, hi): side by
 // side when all are whole fast-mode chunks, else one after another.
-template <int UL, int S>
-__device__ __forceinline__ int walk_lane_states(cptr<RowW> R, int n, int m, int mode, uint64_t c,
+template <int UL, int S, typename RP>
+__device__ __forceinline__ int walk_lane_states(RP R, int n, int m, int mode, uint64_t c,
                                                 uint64_t lo, uint64_t hi, const StaticRows<UL> &sr)
 {
     if (S > 1 && mode == MODE_FAST) {
@@ -114,14 +114,11 @@ __device__ __forceinline__ int target_chunk_log(const PlanArgs &a, double total_
     return (63 - __builtin_clzll((uint64_t)per_task)) - 6 - a.states_log;
 }
 
-// The plan of matrix k: its mode, chunk log, block log, Gray range and task
-// count (row_base is filled in later).  Clears the matrix's tally and
-// completion count, sets its status (always for an invalid order, otherwise
-// only with write_status: a packer running beside the plan owns it then), and
-// writes the result of matrices that need no walk.
-__device__ MatMeta plan_matrix(const PlanArgs &a, int k, int target_m, bool write_status)
+// The plan of a matrix of order n (invalid outside 0..63): its mode, chunk
+// log, block log, Gray range and task count; row_base is filled in later.
+// Pure: reads and writes no memory.
+__device__ MatMeta plan_pure(const PlanArgs &a, int n, int target_m)
 {
-    const int n = a.ns[k];
     const bool valid = n >= 0 && n <= 63;
     MatMeta mt;
     mt.n = valid ? n : 0;
@@ -133,6 +130,58 @@ __device__ MatMeta plan_matrix(const PlanArgs &a, int k, int target_m, bool writ
     mt.hi = 0;
     mt.c_first = 0;
     mt.ul = a.body_log;
+    if (!valid || n == 0) return mt;
+    uint64_t lo, hi;
+    range_of(a, n, lo, hi);
+    mt.lo = lo;
+    mt.hi = hi;
+    const int slog = a.states_log;
+    const int ul = n <= a.mid_max_n ? a.body_log_mid : a.body_log;
+    mt.ul = ul;
+    const bool fast_ok = n >= ul + 7 + slog && n > a.direct_max_n;
+    int m;
+    if (fast_ok) {
+        // a lane's int32 tally covers S chunks and a wave sums 64 lanes: S * 2^m <= 2^24
+        int mmax = a.chunk_log_max < n - 6 - slog ? a.chunk_log_max : n - 6 - slog;
+        if (mmax > 24 - slog) mmax = 24 - slog;
+        // at most 2^max_tasks_log tasks for this matrix, unless its tasks
+        // would then exceed 2^min_task_log indices: every task ends with an
+        // atomic on the matrix's counters, and those serialise
+        const int fewer = n - 6 - slog - a.max_tasks_log;
+        const int longest = a.min_task_log - 6 - slog;
+        const int mfloor = fewer < longest ? fewer : longest;
+        m = target_m > mfloor ? target_m : mfloor;
+        if (m > mmax) m = mmax;
+        if (m < ul + 1) m = ul + 1;
+        mt.mode = MODE_FAST;
+    } else {
+        m = n - 6;
+        if (m > a.direct_chunk_log_max) m = a.direct_chunk_log_max;
+        if (m < 0) m = 0;
+        mt.mode = MODE_DIRECT;
+    }
+    mt.m = m;
+    if (hi > lo) {
+        const uint64_t c0 = lo >> m;
+        const uint64_t c1 = (hi - 1) >> m;
+        mt.c_first = c0;
+        const uint64_t per_task = 64ull << a.states_log;
+        mt.ntasks = (c1 - c0 + per_task) / per_task;
+    } else {
+        mt.mode = MODE_NONE;
+    }
+    return mt;
+}
+
+// The plan of matrix k with its side effects: clears the matrix's tally and
+// completion count, sets its status (always for an invalid order, otherwise
+// only with write_status: a packer running beside the plan owns it then), and
+// writes the result of matrices that need no walk.
+__device__ MatMeta plan_matrix(const PlanArgs &a, int k, int target_m, bool write_status)
+{
+    const int n = a.ns[k];
+    const bool valid = n >= 0 && n <= 63;
+    const MatMeta mt = plan_pure(a, n, target_m);
     a.tally[k] = 0;
     a.done[k] = 0;
     if (write_status || !valid) a.status[k] = valid ? 0 : 1;
@@ -148,47 +197,8 @@ __device__ MatMeta plan_matrix(const PlanArgs &a, int k, int target_m, bool writ
         const uint8_t r = finish_mod3(0, T);
         a.out[k] = r;
         if (a.hist) atomicAdd((unsigned long long *)&a.hist[r], 1ull);
-    } else {
-        uint64_t lo, hi;
-        range_of(a, n, lo, hi);
-        mt.lo = lo;
-        mt.hi = hi;
-        const int slog = a.states_log;
-        const int ul = n <= a.mid_max_n ? a.body_log_mid : a.body_log;
-        mt.ul = ul;
-        const bool fast_ok = n >= ul + 7 + slog && n > a.direct_max_n;
-        int m;
-        if (fast_ok) {
-            // a lane's int32 tally covers S chunks and a wave sums 64 lanes: S * 2^m <= 2^24
-            int mmax = a.chunk_log_max < n - 6 - slog ? a.chunk_log_max : n - 6 - slog;
-            if (mmax > 24 - slog) mmax = 24 - slog;
-            // at most 2^max_tasks_log tasks for this matrix, unless its tasks
-            // would then exceed 2^min_task_log indices: every task ends with an
-            // atomic on the matrix's counters, and those serialise
-            const int fewer = n - 6 - slog - a.max_tasks_log;
-            const int longest = a.min_task_log - 6 - slog;
-            const int mfloor = fewer < longest ? fewer : longest;
-            m = target_m > mfloor ? target_m : mfloor;
-            if (m > mmax) m = mmax;
-            if (m < ul + 1) m = ul + 1;
-            mt.mode = MODE_FAST;
-        } else {
-            m = n - 6;
-            if (m > a.direct_chunk_log_max) m = a.direct_chunk_log_max;
-            if (m < 0) m = 0;
-            mt.mode = MODE_DIRECT;
-        }
-        mt.m = m;
-        if (hi > lo) {
-            const uint64_t c0 = lo >> m;
-            const uint64_t c1 = (hi - 1) >> m;
-            mt.c_first = c0;
-            const uint64_t per_task = 64ull << a.states_log;
-            mt.ntasks = (c1 - c0 + per_task) / per_task;
-        } else {
-            mt.mode = MODE_NONE;
-            a.out[k] = finish_mod3(n, 0);
-        }
+    } else if (mt.mode == MODE_NONE) {
+        a.out[k] = finish_mod3(n, 0);   // empty range
     }
     return mt;
 }
@@ -441,23 +451,11 @@ __device__ void pack_small(const PlanArgs &a, const PackU8Args &pk, int j)
     store_row(pk.rows + s_base + t, mag, sgn);
 }
 
-// A call of up to SMALL_PLAN_MAX matrices: block 0 plans; for byte matrices,
-// block 1 + j packs matrix j in the same launch (no dependence on the plan).
-__global__ void __launch_bounds__(SMALL_BLOCK) k_plan_small(PlanArgs a, PackU8Args pk, int pack)
-{
-    if (blockIdx.x == 0) {
-        if (threadIdx.x >= 64) return;
-        plan_small(a, pack == 0);
-    } else {
-        pack_small(a, pk, blockIdx.x - 1);
-    }
-}
-
 // ------------------------------------------------------------------ walk
 
 // One task of one matrix: the lane's S chunks, with the matrix's block length.
-template <int UL, int S>
-__device__ __forceinline__ int walk_task(cptr<RowW> R, const MatMeta &mt, uint64_t c)
+template <int UL, int S, typename RP>
+__device__ __forceinline__ int walk_task(RP R, const MatMeta &mt, uint64_t c)
 {
     StaticRows<UL> sr;
     if (mt.mode == MODE_FAST) load_static_rows<UL>(R, sr);
@@ -510,6 +508,206 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
                     const uint8_t r = finish_mod3(mt.n, T);
                     a.out[k] = r;
                     if (a.hist) atomicAdd((unsigned long long *)&a.hist[3 * mt.n + r], 1ull);
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ one-launch small calls
+
+// A call of up to SMALL_PLAN_MAX byte matrices with at most SMALL_FUSED_WORK
+// Gray indices in all is planned, packed and walked by one launch: every wave
+// plans the whole call in registers (lane k holds matrix k), takes tasks
+// tau = wave, wave + waves, ... in rank order, packs its task's matrix into
+// its own LDS (one coalesced read of the bytes) and walks it from there.  No
+// result of another kernel is waited on, so the chain of dependent memory
+// reads is short.  The per-matrix accumulators are left at zero by the wave
+// that completes each matrix, ready for the next call.  A larger call is
+// planned and packed here into the work buffers, and k_walk follows.
+
+struct SmallLds {
+    uint8_t bytes[64 * 64];
+    RowW rows[64];
+};
+typedef const __attribute__((address_space(3))) RowW *lds_rows;
+
+__device__ __forceinline__ double readlane_f64(double v, int j)
+{
+    return __longlong_as_double((long long)readlane64((uint64_t)__double_as_longlong(v), j));
+}
+
+__device__ __forceinline__ MatMeta readlane_meta(const MatMeta &v, int j)
+{
+    MatMeta r;
+    r.n = __builtin_amdgcn_readlane(v.n, j);
+    r.m = __builtin_amdgcn_readlane(v.m, j);
+    r.mode = __builtin_amdgcn_readlane(v.mode, j);
+    r.ul = __builtin_amdgcn_readlane(v.ul, j);
+    r.ntasks = readlane64(v.ntasks, j);
+    r.row_base = (int64_t)readlane64((uint64_t)v.row_base, j);
+    r.lo = readlane64(v.lo, j);
+    r.hi = readlane64(v.hi, j);
+    r.c_first = readlane64(v.c_first, j);
+    return r;
+}
+
+// Order the wave's LDS accesses: the rows one lane writes are read by others.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// phi (Section 2) of the n x n byte matrix at src into the wave's LDS rows;
+// returns whether any entry is outside {0, 1, 2} (wave-uniform).
+__device__ bool pack_lds(const uint8_t *src, int n, SmallLds &L, int lane)
+{
+    const int nn = n * n;
+    for (int base = 0; base < nn; base += 64 * 16) {
+        uint8_t v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int idx = base + lane + 64 * i;
+            v[i] = idx < nn ? src[idx] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) L.bytes[base + lane + 64 * i] = v[i];   // base <= 3072: inside
+    }
+    wave_lds_sync();
+    bool bad = false;
+    if (lane < n) {
+        const uint8_t *row = L.bytes + lane * n;
+        uint64_t mag = 0, sgn = 0;
+        for (int c = 0; c < n; ++c) {
+            const uint8_t x = row[c];
+            const uint64_t bit = 1ull << (n - 1 - c);
+            bad |= x > 2;
+            if (x != 0) mag |= bit;
+            if (x == 2) sgn |= bit;
+        }
+        const uint64_t sn = sgn ^ mag;
+        RowW r;
+        r.m_lo = (uint32_t)mag;
+        r.s_lo = (uint32_t)sgn;
+        r.sn_lo = (uint32_t)sn;
+        r.pad0 = 0;
+        r.m_hi = (uint32_t)(mag >> 32);
+        r.s_hi = (uint32_t)(sgn >> 32);
+        r.sn_hi = (uint32_t)(sn >> 32);
+        r.pad1 = 0;
+        L.rows[lane] = r;
+    }
+    const bool any_bad = __any(bad) != 0;
+    wave_lds_sync();
+    return any_bad;
+}
+
+template <int S>
+__global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk, SmallAcc acc, int pack,
+                                                      int allow_fused)
+{
+    static_assert(WALK_BLOCK == SMALL_BLOCK, "one block shape for both roles");
+    __shared__ SmallLds lds[WALK_BLOCK / 64];
+    const int lane = threadIdx.x & 63;
+    const int count = a.count;
+    const bool have = lane < count;
+    const int n = have ? a.ns[lane] : -1;
+    const int64_t off = have && pack ? pk.offs[lane] : 0;
+    const bool valid = have && n >= 0 && n <= 63;
+    double w = 0.0;
+    if (valid) {
+        uint64_t lo, hi;
+        range_of(a, n, lo, hi);
+        w = (double)(hi - lo);
+    }
+    double total_work = 0.0;
+    for (int j = 0; j < count; ++j) total_work += readlane_f64(w, j);
+    if (!(pack && allow_fused && total_work <= (double)SMALL_FUSED_WORK)) {
+        if (blockIdx.x == 0) {
+            if (threadIdx.x < 64) plan_small(a, pack == 0);
+        } else if (pack && (int)blockIdx.x <= count) {
+            pack_small(a, pk, blockIdx.x - 1);
+        }
+        return;
+    }
+
+    const int target_m = target_chunk_log(a, total_work);
+    const MatMeta mt = plan_pure(a, valid ? n : -1, target_m);
+    const uint64_t ntasks = have ? mt.ntasks : 0;
+    const int key = have ? (valid ? n : -1) : -2;   // larger n first
+    uint64_t first = 0, total = 0;
+    for (int j = 0; j < count; ++j) {
+        const int kj = __builtin_amdgcn_readlane(key, j);
+        const uint64_t tj = readlane64(ntasks, j);
+        if (kj > key || (kj == key && j < lane)) first += tj;
+        total += tj;
+    }
+    const uint32_t wi = wave_index();
+    if (wi == 0) {
+        // matrices with no tasks: an invalid order, or n = 0 (one empty
+        // subset, a term of +1: perm of the 0 x 0 matrix is 1)
+        if (have && ntasks == 0) {
+            if (!valid) {
+                a.out[lane] = 0xFF;
+            } else {
+                const uint8_t r = finish_mod3(0, 1);
+                a.out[lane] = r;
+                if (a.hist) atomicAdd((unsigned long long *)&a.hist[r], 1ull);
+            }
+        }
+        if (lane == 0) a.counters[CNT_TOTAL_TASKS] = 0;   // nothing left for a k_walk that follows
+    }
+
+    SmallLds &L = lds[threadIdx.x >> 6];
+    const lds_rows R = (lds_rows)L.rows;
+    const uint32_t nwaves = gridDim.x * (WALK_BLOCK / 64);
+    int packed = -1;
+    bool bad = false;
+    for (uint64_t tau = wi; tau < total; tau += nwaves) {
+        const bool mine = ntasks > 0 && first <= tau && tau < first + ntasks;
+        const int k = __builtin_amdgcn_readfirstlane(__builtin_ctzll(__ballot(mine)));
+        const MatMeta m = readlane_meta(mt, k);
+        const uint64_t q = tau - readlane64(first, k);
+        if (k != packed) {
+            bad = pack_lds(pk.mats + (int64_t)readlane64((uint64_t)off, k), m.n, L, lane);
+            packed = k;
+        }
+        int tally = 0;
+        if (!bad) {
+            const uint64_t c = m.c_first + q * (64u * S) + (uint64_t)lane;
+            if (m.ul == 4)
+                tally = walk_task<4, S>(R, m, c);
+            else if (m.ul == 6)
+                tally = walk_task<6, S>(R, m, c);
+            else
+                tally = walk_task<5, S>(R, m, c);
+        }
+        const int sum = wave_sum(tally);
+        if (lane == 0) {
+            bool last = m.ntasks == 1;
+            long long T = sum;
+            if (!last) {
+                if (sum != 0) atomicAdd((unsigned long long *)&acc.tally[k], (unsigned long long)(long long)sum);
+                __threadfence();
+                const uint64_t prev = atomicAdd((unsigned long long *)&acc.done[k], 1ull);
+                if (prev + 1 == m.ntasks) {
+                    __threadfence();
+                    T = __hip_atomic_load((long long *)&acc.tally[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store((long long *)&acc.tally[k], 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store((unsigned long long *)&acc.done[k], 0ull, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    last = true;
+                }
+            }
+            if (last) {
+                if (bad) {
+                    a.out[k] = 0xFF;
+                } else {
+                    const uint8_t r = finish_mod3(m.n, T);
+                    a.out[k] = r;
+                    if (a.hist) atomicAdd((unsigned long long *)&a.hist[3 * m.n + r], 1ull);
                 }
             }
         }
@@ -611,10 +809,17 @@ hipError_t launch_plan(const PlanArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_plan_small(const PlanArgs &a, const PackU8Args &pk, bool pack, hipStream_t st)
+hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const SmallAcc &acc, bool pack, bool allow_fused,
+                        int states, int blocks, hipStream_t st)
 {
-    if (a.count < 1 || a.count > SMALL_PLAN_MAX) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_plan_small, dim3(1 + (pack ? a.count : 0)), dim3(SMALL_BLOCK), 0, st, a, pk, pack ? 1 : 0);
+    if (a.count < 1 || a.count > SMALL_PLAN_MAX || blocks < a.count + 1) return hipErrorInvalidValue;
+    const int p = pack ? 1 : 0, f = allow_fused ? 1 : 0;
+    switch (states) {
+    case 1: hipLaunchKernelGGL(k_small<1>, dim3(blocks), dim3(WALK_BLOCK), 0, st, a, pk, acc, p, f); break;
+    case 2: hipLaunchKernelGGL(k_small<2>, dim3(blocks), dim3(WALK_BLOCK), 0, st, a, pk, acc, p, f); break;
+    case 4: hipLaunchKernelGGL(k_small<4>, dim3(blocks), dim3(WALK_BLOCK), 0, st, a, pk, acc, p, f); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

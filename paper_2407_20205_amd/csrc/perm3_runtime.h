@@ -52,6 +52,7 @@ struct Launch {
     uint64_t *hist_dev;
     int32_t use_range;
     uint64_t range_lo, range_hi;
+    int32_t fused_only;           // the caller knows the call is walked by k_small alone
 };
 
 using GraphKey = std::tuple<int, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, int, int>;
@@ -67,6 +68,7 @@ struct Context {
 
     DevBuf meta, order, task_start, tally, done, status, counters, rowbuf;
     DevBuf d_stage, d_out, d_census, d_gen, d_wide;
+    DevBuf small_acc;                // SmallAcc: 2 x SMALL_PLAN_MAX words, zero between calls
     HostBuf h_stage, h_wide;
 
     std::map<GraphKey, hipGraphExec_t> graphs;

@@ -184,6 +184,8 @@ int32_t get_context(Context **out)
     HIP_TRY(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    HIP_TRY(c->small_acc.reserve(2 * SMALL_PLAN_MAX * sizeof(uint64_t)));
+    HIP_TRY(hipMemset(c->small_acc.p, 0, 2 * SMALL_PLAN_MAX * sizeof(uint64_t)));
     *out = c.get();
     g_ctx[dev] = std::move(c);
     return PERM_OK;
@@ -300,21 +302,38 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
     pk.rows = (RowW *)rowbuf.p;
     pk.status = (uint8_t *)status.p;
     const bool small = L.count <= SMALL_PLAN_MAX;
-    if (small)
-        HIP_TRY(launch_plan_small(pa, pk, L.pack_kind == 0, st));   // byte matrices packed in the same launch
-    else
-        HIP_TRY(launch_plan(pa, st));
-    if (L.pack_kind == 0) {
-        if (!small) HIP_TRY(launch_pack_u8(pk, st));
+    const bool bytes = L.pack_kind == 0;
+    if (small) {
+        // one launch plans, packs byte matrices and, for little work, walks too
+        SmallAcc sa;
+        sa.tally = (int64_t *)small_acc.p;
+        sa.done = (uint64_t *)small_acc.p + SMALL_PLAN_MAX;
+        const bool fused_ok = bytes && !L.use_range;
+        if (timed && L.fused_only) HIP_TRY(hipEventRecord(ev_walk0, st));
+        HIP_TRY(launch_small(pa, pk, sa, bytes, fused_ok, tuning.states_per_lane,
+                             std::max(grid_blocks(), L.count + 1), st));
+        if (L.fused_only) {
+            if (timed) {
+                HIP_TRY(hipEventRecord(ev_walk1, st));
+                HIP_TRY(hipEventRecord(ev_all1, st));
+            }
+            last_timing_valid = timed;
+            last_launches = 1;
+            return PERM_OK;
+        }
     } else {
-        PackPlanesArgs pk;
-        pk.planes = L.planes_dev;
-        pk.row_off = L.row_off_dev;
-        pk.meta = (const MatMeta *)meta.p;
-        pk.count = L.count;
-        pk.rows = (RowW *)rowbuf.p;
-        pk.status = (uint8_t *)status.p;
-        HIP_TRY(launch_pack_planes(pk, st));
+        HIP_TRY(launch_plan(pa, st));
+        if (bytes) HIP_TRY(launch_pack_u8(pk, st));
+    }
+    if (!bytes) {
+        PackPlanesArgs pp;
+        pp.planes = L.planes_dev;
+        pp.row_off = L.row_off_dev;
+        pp.meta = (const MatMeta *)meta.p;
+        pp.count = L.count;
+        pp.rows = (RowW *)rowbuf.p;
+        pp.status = (uint8_t *)status.p;
+        HIP_TRY(launch_pack_planes(pp, st));
     }
     if (timed) HIP_TRY(hipEventRecord(ev_walk0, st));
     HIP_TRY(launch_walk(walk_args(L.count, L.out_dev, L.hist_dev), tuning.states_per_lane, grid_blocks(), st));
@@ -323,7 +342,7 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
         HIP_TRY(hipEventRecord(ev_all1, st));
     }
     last_timing_valid = timed;
-    last_launches = small && L.pack_kind == 0 ? 2 : 3;
+    last_launches = small && bytes ? 2 : 3;
     return PERM_OK;
 }
 
@@ -372,7 +391,7 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
     }
     HIP_TRY(hipGraphLaunch(it->second, st));
     last_timing_valid = false;
-    last_launches = L.count <= SMALL_PLAN_MAX && L.pack_kind == 0 ? 2 : 3;
+    last_launches = 3;   // graphs are used for calls of more than SMALL_PLAN_MAX matrices only
     return mark(st);
 }
 
@@ -443,6 +462,11 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     L.use_range = use_range ? 1 : 0;
     L.range_lo = lo;
     L.range_hi = hi;
+    // the orders are known here: a small call whose walk k_small takes alone
+    // needs no k_walk after it (the kernel makes the same decision)
+    uint64_t work = 0;
+    for (int32_t k = 0; k < count; ++k) work += 1ull << ns[k];
+    L.fused_only = count <= SMALL_PLAN_MAX && !use_range && work <= SMALL_FUSED_WORK ? 1 : 0;
     rc = run(L, st, false);
     if (rc) return rc;
     if (out_host) HIP_TRY(hipMemcpyAsync(out_host, d_out.p, (size_t)count, hipMemcpyDeviceToHost, st));
