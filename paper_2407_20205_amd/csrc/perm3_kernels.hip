@@ -144,10 +144,13 @@ __device__ MatMeta plan_pure(const PlanArgs &a, int n, int target_m)
         // a lane's int32 tally covers S chunks and a wave sums 64 lanes: S * 2^m <= 2^24
         int mmax = a.chunk_log_max < n - 6 - slog ? a.chunk_log_max : n - 6 - slog;
         if (mmax > 24 - slog) mmax = 24 - slog;
-        // at most 2^max_tasks_log tasks for this matrix, unless its tasks
-        // would then exceed 2^min_task_log indices: every task ends with an
-        // atomic on the matrix's counters, and those serialise
-        const int fewer = n - 6 - slog - a.max_tasks_log;
+        // at most 2^max_tasks_log tasks for this matrix, and at most about
+        // 2^(n/2) for a small one (a task's fixed cost, its seed and its
+        // cold start, then outweighs the walk it shares out), unless its
+        // tasks would then exceed 2^min_task_log indices: every task ends
+        // with an atomic on the matrix's counters, and those serialise
+        const int tasks_log = (n - 3) / 2 < a.max_tasks_log ? (n - 3) / 2 : a.max_tasks_log;
+        const int fewer = n - 6 - slog - tasks_log;
         const int longest = a.min_task_log - 6 - slog;
         const int mfloor = fewer < longest ? fewer : longest;
         m = target_m > mfloor ? target_m : mfloor;
