@@ -304,27 +304,74 @@ __device__ __forceinline__ void store_row(RowW *dst, uint64_t mag, uint64_t sgn)
 
 // phi (Section 2): mag bit = (a != 0), sgn bit = (a == -1); element j of a
 // row goes to bit n-1-j, so (1,1,0,-1) becomes (0xd, 0x1).
-__global__ void __launch_bounds__(64) k_pack_u8(PackU8Args a)
+// phi (Section 2) of one row of n bytes: column c at bit n-1-c of the mag
+// and sgn words; returns whether an entry is outside {0, 1, 2}.
+__device__ __forceinline__ bool phi_row(const uint8_t *row, int n, uint64_t &mag, uint64_t &sgn)
+{
+    mag = 0;
+    sgn = 0;
+    bool bad = false;
+    for (int c = 0; c < n; ++c) {
+        const uint8_t x = row[c];
+        const uint64_t bit = 1ull << (n - 1 - c);
+        bad |= x > 2;
+        if (x != 0) mag |= bit;
+        if (x == 2) sgn |= bit;
+    }
+    return bad;
+}
+
+// The n x n bytes at src (n <= 63: at most 3969) copied into dst (4096 bytes
+// of LDS) by NT cooperating threads, thread t of them, each with its 16
+// loads in flight together.  A round covers NT * 16 bytes, which divides
+// 4096, so every round that starts below n * n <= 4096 ends inside dst.
+template <int NT>
+__device__ __forceinline__ void stage_bytes(const uint8_t *src, int n, uint8_t *dst, int t)
+{
+    static_assert(4096 % (NT * 16) == 0, "rounds tile the 4096-byte buffer");
+    const int nn = n * n;
+    for (int base = 0; base < nn; base += NT * 16) {
+        uint8_t v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int idx = base + t + NT * i;
+            v[i] = idx < nn ? src[idx] : 0;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int idx = base + t + NT * i;
+            dst[idx] = v[i];
+        }
+    }
+}
+
+constexpr int PACK_BLOCK = 256;
+
+// phi of one byte matrix (1 <= n <= 63) by a PACK_BLOCK-thread block: its
+// bytes read once into LDS, row r formed by thread r; the matrix's status is
+// set to whether any entry is outside {0, 1, 2}.  Every thread of the block
+// must call it.
+__device__ void pack_block(const uint8_t *src, int n, RowW *dst, uint8_t *status)
+{
+    __shared__ uint8_t s_mat[4096];
+    const int t = threadIdx.x;
+    stage_bytes<PACK_BLOCK>(src, n, s_mat, t);
+    __syncthreads();
+    if (t >= 64) return;                       // n <= 63: every row is in wave 0
+    uint64_t mag = 0, sgn = 0;
+    const bool bad = t < n ? phi_row(s_mat + t * n, n, mag, sgn) : false;
+    const bool any_bad = __any(bad) != 0;
+    if (t == 0) *status = any_bad ? 1 : 0;
+    if (t < n) store_row(dst + t, mag, sgn);
+}
+
+__global__ void __launch_bounds__(PACK_BLOCK) k_pack_u8(PackU8Args a)
 {
     const int k = blockIdx.x;
     if (k >= a.count) return;
     const MatMeta mt = a.meta[k];
     if (mt.mode == MODE_NONE) return;
-    const int n = mt.n;
-    const int r = threadIdx.x;
-    if (r >= n) return;
-    const uint8_t *row = a.mats + a.offs[k] + (int64_t)r * n;
-    uint64_t mag = 0, sgn = 0;
-    bool bad = false;
-    for (int j = 0; j < n; ++j) {
-        const uint8_t v = row[j];
-        const uint64_t bit = 1ull << (n - 1 - j);
-        bad |= v > 2;
-        if (v != 0) mag |= bit;
-        if (v == 2) sgn |= bit;
-    }
-    if (bad) a.status[k] = 1;
-    store_row(a.rows + mt.row_base + r, mag, sgn);
+    pack_block(a.mats + a.offs[k], mt.n, a.rows + mt.row_base, a.status + k);
 }
 
 __global__ void __launch_bounds__(64) k_pack_planes(PackPlanesArgs a)
@@ -346,7 +393,6 @@ __global__ void __launch_bounds__(64) k_pack_planes(PackPlanesArgs a)
 
 // ------------------------------------------------------------------ small calls
 
-constexpr int SMALL_BLOCK = 256;
 
 // Lane j's value of a 64-bit variable, read by every lane (j wave-uniform).
 __device__ __forceinline__ uint64_t readlane64(uint64_t v, int j)
@@ -413,7 +459,6 @@ __device__ void plan_small(const PlanArgs &a, bool write_status)
 // plan).  This block alone writes the matrix's status when its order is valid.
 __device__ void pack_small(const PlanArgs &a, const PackU8Args &pk, int j)
 {
-    __shared__ uint8_t s_mat[SMALL_BLOCK * 16];
     __shared__ long long s_base;
     const int t = threadIdx.x;
     const int n = a.ns[j];
@@ -427,31 +472,8 @@ __device__ void pack_small(const PlanArgs &a, const PackU8Args &pk, int j)
         const long long base = wave_sum_i64(ni >= 0 && ni <= 63 ? ni : 0);
         if (t == 0) s_base = base;
     }
-    const int nn = n * n;
-    const uint8_t *src = pk.mats + pk.offs[j];
-    uint8_t v[16];
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const int idx = t + SMALL_BLOCK * i;
-        v[i] = idx < nn ? src[idx] : 0;
-    }
-#pragma unroll
-    for (int i = 0; i < 16; ++i) s_mat[t + SMALL_BLOCK * i] = v[i];
     __syncthreads();
-    if (t >= n) return;
-    const uint8_t *row = s_mat + t * n;
-    uint64_t mag = 0, sgn = 0;
-    bool bad = false;
-    for (int c = 0; c < n; ++c) {
-        const uint8_t x = row[c];
-        const uint64_t bit = 1ull << (n - 1 - c);
-        bad |= x > 2;
-        if (x != 0) mag |= bit;
-        if (x == 2) sgn |= bit;
-    }
-    bad = __any(bad);
-    if (t == 0) pk.status[j] = bad ? 1 : 0;
-    store_row(pk.rows + s_base + t, mag, sgn);
+    pack_block(pk.mats + pk.offs[j], n, pk.rows + s_base, pk.status + j);
 }
 
 // ------------------------------------------------------------------ walk
@@ -567,29 +589,11 @@ __device__ __forceinline__ void wave_lds_sync()
 // returns whether any entry is outside {0, 1, 2} (wave-uniform).
 __device__ bool pack_lds(const uint8_t *src, int n, SmallLds &L, int lane)
 {
-    const int nn = n * n;
-    for (int base = 0; base < nn; base += 64 * 16) {
-        uint8_t v[16];
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            const int idx = base + lane + 64 * i;
-            v[i] = idx < nn ? src[idx] : 0;
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) L.bytes[base + lane + 64 * i] = v[i];   // base <= 3072: inside
-    }
+    stage_bytes<64>(src, n, L.bytes, lane);
     wave_lds_sync();
-    bool bad = false;
+    uint64_t mag = 0, sgn = 0;
+    const bool bad = lane < n ? phi_row(L.bytes + lane * n, n, mag, sgn) : false;
     if (lane < n) {
-        const uint8_t *row = L.bytes + lane * n;
-        uint64_t mag = 0, sgn = 0;
-        for (int c = 0; c < n; ++c) {
-            const uint8_t x = row[c];
-            const uint64_t bit = 1ull << (n - 1 - c);
-            bad |= x > 2;
-            if (x != 0) mag |= bit;
-            if (x == 2) sgn |= bit;
-        }
         const uint64_t sn = sgn ^ mag;
         RowW r;
         r.m_lo = (uint32_t)mag;
@@ -611,7 +615,7 @@ template <int S>
 __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk, SmallAcc acc, int pack,
                                                       int allow_fused)
 {
-    static_assert(WALK_BLOCK == SMALL_BLOCK, "one block shape for both roles");
+    static_assert(WALK_BLOCK == PACK_BLOCK, "one block shape for both roles");
     __shared__ SmallLds lds[WALK_BLOCK / 64];
     const int lane = threadIdx.x & 63;
     const int count = a.count;
@@ -829,7 +833,7 @@ hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const SmallAcc 
 hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st)
 {
     if (a.count <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pack_u8, dim3(a.count), dim3(64), 0, st, a);
+    hipLaunchKernelGGL(k_pack_u8, dim3(a.count), dim3(PACK_BLOCK), 0, st, a);
     return hipGetLastError();
 }
 
