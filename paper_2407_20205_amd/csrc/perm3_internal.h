@@ -128,7 +128,7 @@ struct SmallAcc {
     uint64_t *done;     // SMALL_PLAN_MAX entries
 };
 hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const SmallAcc &acc, bool pack, bool allow_fused,
-                        int states, int blocks, hipStream_t st);
+                        int blocks, hipStream_t st);
 hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st);
 hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st);
 hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st);

@@ -611,7 +611,6 @@ __device__ bool pack_lds(const uint8_t *src, int n, SmallLds &L, int lane)
     return any_bad;
 }
 
-template <int S>
 __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk, SmallAcc acc, int pack,
                                                       int allow_fused)
 {
@@ -640,8 +639,11 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk,
         return;
     }
 
-    const int target_m = target_chunk_log(a, total_work);
-    const MatMeta mt = plan_pure(a, valid ? n : -1, target_m);
+    // one chunk per lane: carrying several side by side pays only on long tasks
+    PlanArgs pf = a;
+    pf.states_log = 0;
+    const int target_m = target_chunk_log(pf, total_work);
+    const MatMeta mt = plan_pure(pf, valid ? n : -1, target_m);
     const uint64_t ntasks = have ? mt.ntasks : 0;
     const int key = have ? (valid ? n : -1) : -2;   // larger n first
     uint64_t first = 0, total = 0;
@@ -683,13 +685,13 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk,
         }
         int tally = 0;
         if (!bad) {
-            const uint64_t c = m.c_first + q * (64u * S) + (uint64_t)lane;
+            const uint64_t c = m.c_first + q * 64u + (uint64_t)lane;
             if (m.ul == 4)
-                tally = walk_task<4, S>(R, m, c);
+                tally = walk_task<4, 1>(R, m, c);
             else if (m.ul == 6)
-                tally = walk_task<6, S>(R, m, c);
+                tally = walk_task<6, 1>(R, m, c);
             else
-                tally = walk_task<5, S>(R, m, c);
+                tally = walk_task<5, 1>(R, m, c);
         }
         const int sum = wave_sum(tally);
         if (lane == 0) {
@@ -817,16 +819,10 @@ hipError_t launch_plan(const PlanArgs &a, hipStream_t st)
 }
 
 hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const SmallAcc &acc, bool pack, bool allow_fused,
-                        int states, int blocks, hipStream_t st)
+                        int blocks, hipStream_t st)
 {
     if (a.count < 1 || a.count > SMALL_PLAN_MAX || blocks < a.count + 1) return hipErrorInvalidValue;
-    const int p = pack ? 1 : 0, f = allow_fused ? 1 : 0;
-    switch (states) {
-    case 1: hipLaunchKernelGGL(k_small<1>, dim3(blocks), dim3(WALK_BLOCK), 0, st, a, pk, acc, p, f); break;
-    case 2: hipLaunchKernelGGL(k_small<2>, dim3(blocks), dim3(WALK_BLOCK), 0, st, a, pk, acc, p, f); break;
-    case 4: hipLaunchKernelGGL(k_small<4>, dim3(blocks), dim3(WALK_BLOCK), 0, st, a, pk, acc, p, f); break;
-    default: return hipErrorInvalidValue;
-    }
+    hipLaunchKernelGGL(k_small, dim3(blocks), dim3(WALK_BLOCK), 0, st, a, pk, acc, pack ? 1 : 0, allow_fused ? 1 : 0);
     return hipGetLastError();
 }
 

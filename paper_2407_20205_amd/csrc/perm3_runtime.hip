@@ -310,8 +310,7 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
         sa.done = (uint64_t *)small_acc.p + SMALL_PLAN_MAX;
         const bool fused_ok = bytes && !L.use_range;
         if (timed && L.fused_only) HIP_TRY(hipEventRecord(ev_walk0, st));
-        HIP_TRY(launch_small(pa, pk, sa, bytes, fused_ok, tuning.states_per_lane,
-                             std::max(grid_blocks(), L.count + 1), st));
+        HIP_TRY(launch_small(pa, pk, sa, bytes, fused_ok, std::max(grid_blocks(), L.count + 1), st));
         if (L.fused_only) {
             if (timed) {
                 HIP_TRY(hipEventRecord(ev_walk1, st));

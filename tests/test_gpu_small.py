@@ -105,8 +105,13 @@ def test_orders_zero_invalid_and_bad_entries_with_histogram():
 
 @pytest.mark.parametrize("states", [1, 2, 4])
 def test_states_per_lane(states):
+    """The one-launch walk carries one chunk per lane whatever the tuning; the longer path (here a
+    Gray range of a 26x26, planned by the same launch) follows the tuning."""
     ns, mats = mixed(8, 14, 26, 4030 + states)
     want = np.array(oracle_perms(mats), np.uint8)
+    A = W.uniform_matrix(26, 4035)
+    lo, hi = 12345, (1 << 25) + 777
+    want_t = oracle.range_tally(A, lo, hi)
     base = P.tuning_get()
     try:
         t = P.tuning_get()
@@ -116,6 +121,7 @@ def test_states_per_lane(states):
             got, _ = run_dev(ns, mats)
             assert np.array_equal(got, want)
             assert np.array_equal(P.perm_mod3_batch(mats), want)
+            assert P.perm_mod3_range_tally(A, lo, hi) == want_t
     finally:
         P.tuning_set(base)
 
