@@ -287,7 +287,9 @@ __global__ void __launch_bounds__(1024) k_plan(PlanArgs a)
 
 // ------------------------------------------------------------------ pack
 
-__device__ __forceinline__ void store_row(RowW *dst, uint64_t mag, uint64_t sgn)
+// The walk's row record of a row with words (mag, sgn): both words split in
+// 32-bit halves, with the negated row's sign word sn = sgn ^ mag beside them.
+__device__ __forceinline__ RowW make_row(uint64_t mag, uint64_t sgn)
 {
     RowW r;
     const uint64_t sn = sgn ^ mag;
@@ -299,8 +301,10 @@ __device__ __forceinline__ void store_row(RowW *dst, uint64_t mag, uint64_t sgn)
     r.s_hi = (uint32_t)(sgn >> 32);
     r.sn_hi = (uint32_t)(sn >> 32);
     r.pad1 = 0;
-    *dst = r;
+    return r;
 }
+
+__device__ __forceinline__ void store_row(RowW *dst, uint64_t mag, uint64_t sgn) { *dst = make_row(mag, sgn); }
 
 // phi (Section 2): mag bit = (a != 0), sgn bit = (a == -1); element j of a
 // row goes to bit n-1-j, so (1,1,0,-1) becomes (0xd, 0x1).
@@ -593,19 +597,7 @@ __device__ bool pack_lds(const uint8_t *src, int n, SmallLds &L, int lane)
     wave_lds_sync();
     uint64_t mag = 0, sgn = 0;
     const bool bad = lane < n ? phi_row(L.bytes + lane * n, n, mag, sgn) : false;
-    if (lane < n) {
-        const uint64_t sn = sgn ^ mag;
-        RowW r;
-        r.m_lo = (uint32_t)mag;
-        r.s_lo = (uint32_t)sgn;
-        r.sn_lo = (uint32_t)sn;
-        r.pad0 = 0;
-        r.m_hi = (uint32_t)(mag >> 32);
-        r.s_hi = (uint32_t)(sgn >> 32);
-        r.sn_hi = (uint32_t)(sn >> 32);
-        r.pad1 = 0;
-        L.rows[lane] = r;
-    }
+    if (lane < n) L.rows[lane] = make_row(mag, sgn);
     const bool any_bad = __any(bad) != 0;
     wave_lds_sync();
     return any_bad;
