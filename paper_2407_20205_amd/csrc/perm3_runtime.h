@@ -67,9 +67,10 @@ struct Context {
     std::mutex mu;
 
     DevBuf meta, order, task_start, tally, done, status, counters, rowbuf;
-    DevBuf d_stage, d_out, d_census, d_gen, d_wide;
+    DevBuf d_stage, d_census, d_gen, d_wide;
     DevBuf small_acc;                // SmallAcc: 2 x SMALL_PLAN_MAX words, zero between calls
     HostBuf h_stage, h_wide;
+    HostBuf h_out;                   // host-call results, written by the kernels directly
 
     std::map<GraphKey, hipGraphExec_t> graphs;
     hipEvent_t ev_walk0 = nullptr, ev_walk1 = nullptr, ev_all0 = nullptr, ev_all1 = nullptr;

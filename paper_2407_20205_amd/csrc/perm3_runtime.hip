@@ -430,7 +430,10 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     const size_t stage_bytes = ns_at + ns_bytes;
     HIP_TRY(h_stage.reserve(stage_bytes));
     HIP_TRY(d_stage.reserve(stage_bytes));
-    HIP_TRY(d_out.reserve((size_t)std::max(count, 1)));
+    // results go straight to pinned host memory: no copy after the walk
+    HIP_TRY(h_out.reserve((size_t)std::max(count, 1)));
+    uint8_t *out_dev = nullptr;
+    HIP_TRY(hipHostGetDevicePointer((void **)&out_dev, h_out.p, 0));
     int32_t rc = reserve_work(count, rows);
     if (rc) return rc;
     uint8_t *h = (uint8_t *)h_stage.p;
@@ -456,7 +459,7 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     L.offs_dev = (const int64_t *)(d + offs_at);
     L.ns_dev = (const int32_t *)(d + ns_at);
     L.count = count;
-    L.out_dev = (uint8_t *)d_out.p;
+    L.out_dev = out_dev;
     L.hist_dev = nullptr;
     L.use_range = use_range ? 1 : 0;
     L.range_lo = lo;
@@ -468,9 +471,9 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     L.fused_only = count <= SMALL_PLAN_MAX && !use_range && work <= SMALL_FUSED_WORK ? 1 : 0;
     rc = run(L, st, false);
     if (rc) return rc;
-    if (out_host) HIP_TRY(hipMemcpyAsync(out_host, d_out.p, (size_t)count, hipMemcpyDeviceToHost, st));
     if (tally_host) HIP_TRY(hipMemcpyAsync(tally_host, tally.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (out_host) memcpy(out_host, h_out.p, (size_t)count);
     return PERM_OK;
 }
 
