@@ -159,13 +159,19 @@ int32_t perm_mod3_batch(const uint8_t *const *As, const int32_t *ns, int32_t cou
  *              [0, 63] gets PERM_RESULT_INVALID and is not computed
  *   hist_dev:  device uint64[64*3] or NULL; the counts of results 0/1/2 are
  *              ADDED at hist_dev[3*n + r] (the caller zeroes it)
- *   stream:    a hipStream_t; or NULL: the library's stream, ordered after
- *              earlier and before later work on the legacy default stream
+ *   stream:    a hipStream_t; or NULL: the legacy default stream itself for
+ *              a call of up to 64 matrices (or with graphs off); otherwise
+ *              the library's stream, ordered after earlier and before later
+ *              work on the legacy default stream
  * Asynchronous on `stream`: all steps (validate, pack with phi, plan, Gray
  * walk, reduce, finish) run as kernels; the call returns after enqueueing.
- * The launches of one (pointer, count) signature are captured once into a HIP
- * graph and replayed afterwards.  Buffers must stay valid until the stream
- * reaches the call's end.
+ * A call of up to 64 matrices is two direct launches: one kernel plans and
+ * packs them and, when they hold at most 2^28 Gray indices in all, walks
+ * them too; the persistent walk that follows then finds nothing to do.  The
+ * launches of a larger call are captured once per (pointers, count, stream)
+ * into a HIP graph and replayed afterwards.  Calls into one device are
+ * ordered among themselves, whatever their streams.  Buffers must stay valid
+ * until the stream reaches the call's end.
  */
 int32_t perm_mod3_batch_dev(const uint8_t *mats_dev, const int64_t *offs_dev,
                              const int32_t *ns_dev, int32_t count, uint8_t *out_dev,
@@ -280,11 +286,13 @@ typedef struct {
     int32_t chunk_log_max;    /* largest per-lane chunk, log2 Gray indices (8..24)        */
     int32_t tasks_per_wave;   /* target tasks per persistent wave                         */
     int32_t direct_max_n;     /* n at or below which every step is tested exactly        */
-    int32_t use_graphs;       /* 1: capture device-input calls into cached HIP graphs     */
+    int32_t use_graphs;       /* 1: capture device-input calls of more than 64 matrices
+                                 into cached HIP graphs                                     */
     int32_t states_per_lane;  /* chunks a lane walks side by side: 1, 2 or 4              */
     int32_t body_log_mid;     /* block log2 for direct_max_n < n <= mid_max_n: 4, 5 or 6  */
     int32_t mid_max_n;        /* see body_log_mid                                         */
-    int32_t max_tasks_log;    /* a matrix is cut into at most 2^max_tasks_log tasks ...   */
+    int32_t max_tasks_log;    /* a matrix is cut into at most 2^min(max_tasks_log,
+                                 (n-3)/2) tasks ...                                         */
     int32_t min_task_log;     /* ... unless its tasks would then exceed 2^min_task_log Gray
                                  indices; each task ends with an atomic on its matrix's
                                  counters, and on one address those serialise (0..30)       */
