@@ -127,8 +127,8 @@ struct SmallAcc {
     int64_t *tally;     // SMALL_PLAN_MAX entries
     uint64_t *done;     // SMALL_PLAN_MAX entries
 };
-hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const SmallAcc &acc, bool pack, bool allow_fused,
-                        int blocks, hipStream_t st);
+hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const PackPlanesArgs &pp, const SmallAcc &acc,
+                        int kind, bool allow_fused, int blocks, hipStream_t st);
 hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st);
 hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st);
 hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st);

@@ -378,6 +378,16 @@ __global__ void __launch_bounds__(PACK_BLOCK) k_pack_u8(PackU8Args a)
     pack_block(a.mats + a.offs[k], mt.n, a.rows + mt.row_base, a.status + k);
 }
 
+// Row r of a caller-packed matrix: its (mag, sgn) words at src[2r], src[2r+1];
+// returns whether a bit at or above n is set in either.
+__device__ __forceinline__ bool planes_row(const uint64_t *src, int n, int r, uint64_t &mag, uint64_t &sgn)
+{
+    mag = src[2 * r];
+    sgn = src[2 * r + 1];
+    const uint64_t high = (n >= 64) ? 0 : ~((1ull << n) - 1ull);
+    return ((mag | sgn) & high) != 0;
+}
+
 __global__ void __launch_bounds__(64) k_pack_planes(PackPlanesArgs a)
 {
     const int k = blockIdx.x;
@@ -387,11 +397,8 @@ __global__ void __launch_bounds__(64) k_pack_planes(PackPlanesArgs a)
     const int n = mt.n;
     const int r = threadIdx.x;
     if (r >= n) return;
-    const int64_t src = a.row_off[k] + r;
-    const uint64_t mag = a.planes[2 * src];
-    const uint64_t sgn = a.planes[2 * src + 1];
-    const uint64_t high = (n >= 64) ? 0 : ~((1ull << n) - 1ull);
-    if ((mag | sgn) & high) a.status[k] = 1;
+    uint64_t mag, sgn;
+    if (planes_row(a.planes + 2 * a.row_off[k], n, r, mag, sgn)) a.status[k] = 1;
     store_row(a.rows + mt.row_base + r, mag, sgn);
 }
 
@@ -478,6 +485,22 @@ __device__ void pack_small(const PlanArgs &a, const PackU8Args &pk, int j)
     }
     __syncthreads();
     pack_block(pk.mats + pk.offs[j], n, pk.rows + s_base, pk.status + j);
+}
+
+// The same for caller-packed planes: wave 0 of the block, row r by lane r.
+__device__ void pack_small_planes(const PlanArgs &a, const PackPlanesArgs &pp, int j)
+{
+    const int t = threadIdx.x;
+    if (t >= 64) return;
+    const int n = a.ns[j];
+    if (n < 0 || n > 63) return;                  // the plan marks it invalid
+    const int ni = t < j ? a.ns[t] : 0;
+    const long long base = wave_sum_i64(ni >= 0 && ni <= 63 ? ni : 0);
+    uint64_t mag = 0, sgn = 0;
+    const bool bad = t < n ? planes_row(pp.planes + 2 * pp.row_off[j], n, t, mag, sgn) : false;
+    const bool any_bad = __any(bad) != 0;
+    if (t == 0) pp.status[j] = any_bad ? 1 : 0;
+    if (t < n) store_row(pp.rows + base + t, mag, sgn);
 }
 
 // ------------------------------------------------------------------ walk
@@ -603,8 +626,21 @@ __device__ bool pack_lds(const uint8_t *src, int n, SmallLds &L, int lane)
     return any_bad;
 }
 
-__global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk, SmallAcc acc, int pack,
-                                                      int allow_fused)
+// Caller-packed planes into the wave's LDS rows; returns whether a bit at or
+// above n is set (wave-uniform).
+__device__ bool pack_lds_planes(const uint64_t *src, int n, SmallLds &L, int lane)
+{
+    uint64_t mag = 0, sgn = 0;
+    const bool bad = lane < n ? planes_row(src, n, lane, mag, sgn) : false;
+    if (lane < n) L.rows[lane] = make_row(mag, sgn);
+    const bool any_bad = __any(bad) != 0;
+    wave_lds_sync();
+    return any_bad;
+}
+
+// kind 0: byte matrices (pk); kind 1: caller-packed planes (pp).
+__global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk, PackPlanesArgs pp, SmallAcc acc,
+                                                      int kind, int allow_fused)
 {
     static_assert(WALK_BLOCK == PACK_BLOCK, "one block shape for both roles");
     __shared__ SmallLds lds[WALK_BLOCK / 64];
@@ -612,7 +648,7 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk,
     const int count = a.count;
     const bool have = lane < count;
     const int n = have ? a.ns[lane] : -1;
-    const int64_t off = have && pack ? pk.offs[lane] : 0;
+    const int64_t off = have ? (kind == 0 ? pk.offs[lane] : pp.row_off[lane]) : 0;
     const bool valid = have && n >= 0 && n <= 63;
     double w = 0.0;
     if (valid) {
@@ -622,11 +658,15 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk,
     }
     double total_work = 0.0;
     for (int j = 0; j < count; ++j) total_work += readlane_f64(w, j);
-    if (!(pack && allow_fused && total_work <= (double)SMALL_FUSED_WORK)) {
+    if (!(allow_fused && total_work <= (double)SMALL_FUSED_WORK)) {
+        // block 0 plans; block 1 + j packs matrix j and owns its status
         if (blockIdx.x == 0) {
-            if (threadIdx.x < 64) plan_small(a, pack == 0);
-        } else if (pack && (int)blockIdx.x <= count) {
-            pack_small(a, pk, blockIdx.x - 1);
+            if (threadIdx.x < 64) plan_small(a, false);
+        } else if ((int)blockIdx.x <= count) {
+            if (kind == 0)
+                pack_small(a, pk, blockIdx.x - 1);
+            else
+                pack_small_planes(a, pp, blockIdx.x - 1);
         }
         return;
     }
@@ -672,7 +712,8 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk,
         const MatMeta m = readlane_meta(mt, k);
         const uint64_t q = tau - readlane64(first, k);
         if (k != packed) {
-            bad = pack_lds(pk.mats + (int64_t)readlane64((uint64_t)off, k), m.n, L, lane);
+            const int64_t ok = (int64_t)readlane64((uint64_t)off, k);
+            bad = kind == 0 ? pack_lds(pk.mats + ok, m.n, L, lane) : pack_lds_planes(pp.planes + 2 * ok, m.n, L, lane);
             packed = k;
         }
         int tally = 0;
@@ -810,11 +851,12 @@ hipError_t launch_plan(const PlanArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const SmallAcc &acc, bool pack, bool allow_fused,
-                        int blocks, hipStream_t st)
+hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const PackPlanesArgs &pp, const SmallAcc &acc,
+                        int kind, bool allow_fused, int blocks, hipStream_t st)
 {
-    if (a.count < 1 || a.count > SMALL_PLAN_MAX || blocks < a.count + 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_small, dim3(blocks), dim3(WALK_BLOCK), 0, st, a, pk, acc, pack ? 1 : 0, allow_fused ? 1 : 0);
+    if (a.count < 1 || a.count > SMALL_PLAN_MAX || blocks < a.count + 1 || (kind != 0 && kind != 1))
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_small, dim3(blocks), dim3(WALK_BLOCK), 0, st, a, pk, pp, acc, kind, allow_fused ? 1 : 0);
     return hipGetLastError();
 }
 

@@ -301,16 +301,22 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
     pk.count = L.count;
     pk.rows = (RowW *)rowbuf.p;
     pk.status = (uint8_t *)status.p;
+    PackPlanesArgs pp;
+    pp.planes = L.planes_dev;
+    pp.row_off = L.row_off_dev;
+    pp.meta = (const MatMeta *)meta.p;
+    pp.count = L.count;
+    pp.rows = (RowW *)rowbuf.p;
+    pp.status = (uint8_t *)status.p;
     const bool small = L.count <= SMALL_PLAN_MAX;
     const bool bytes = L.pack_kind == 0;
     if (small) {
-        // one launch plans, packs byte matrices and, for little work, walks too
+        // one launch plans and packs and, for little work, walks too
         SmallAcc sa;
         sa.tally = (int64_t *)small_acc.p;
         sa.done = (uint64_t *)small_acc.p + SMALL_PLAN_MAX;
-        const bool fused_ok = bytes && !L.use_range;
         if (timed && L.fused_only) HIP_TRY(hipEventRecord(ev_walk0, st));
-        HIP_TRY(launch_small(pa, pk, sa, bytes, fused_ok, std::max(grid_blocks(), L.count + 1), st));
+        HIP_TRY(launch_small(pa, pk, pp, sa, bytes ? 0 : 1, !L.use_range, std::max(grid_blocks(), L.count + 1), st));
         if (L.fused_only) {
             if (timed) {
                 HIP_TRY(hipEventRecord(ev_walk1, st));
@@ -322,17 +328,7 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
         }
     } else {
         HIP_TRY(launch_plan(pa, st));
-        if (bytes) HIP_TRY(launch_pack_u8(pk, st));
-    }
-    if (!bytes) {
-        PackPlanesArgs pp;
-        pp.planes = L.planes_dev;
-        pp.row_off = L.row_off_dev;
-        pp.meta = (const MatMeta *)meta.p;
-        pp.count = L.count;
-        pp.rows = (RowW *)rowbuf.p;
-        pp.status = (uint8_t *)status.p;
-        HIP_TRY(launch_pack_planes(pp, st));
+        HIP_TRY(bytes ? launch_pack_u8(pk, st) : launch_pack_planes(pp, st));
     }
     if (timed) HIP_TRY(hipEventRecord(ev_walk0, st));
     HIP_TRY(launch_walk(walk_args(L.count, L.out_dev, L.hist_dev), tuning.states_per_lane, grid_blocks(), st));
@@ -341,7 +337,7 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
         HIP_TRY(hipEventRecord(ev_all1, st));
     }
     last_timing_valid = timed;
-    last_launches = small && bytes ? 2 : 3;
+    last_launches = small ? 2 : 3;
     return PERM_OK;
 }
 

@@ -103,6 +103,48 @@ def test_orders_zero_invalid_and_bad_entries_with_histogram():
     assert np.array_equal(got2, want[ok])
 
 
+def run_packed(ns, planes):
+    """One call on caller-packed planes (uint64 words, mag then sgn per row); returns the results."""
+    import torch
+    row_off = np.zeros(len(ns), np.int64)
+    row_off[1:] = np.cumsum(np.asarray(ns[:-1], np.int64))
+    out = torch.full((len(ns),), 0xEE, dtype=torch.uint8, device="cuda")
+    P.perm_mod3_batch_packed(to_dev(planes.view(np.int64), torch.int64), to_dev(row_off, torch.int64),
+                             to_dev(np.asarray(ns, np.int32), torch.int32), out, None, None)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def test_packed_planes_one_launch_and_longer_path():
+    """Caller-packed planes take the same two paths: packed into each wave's LDS and walked in the
+    same launch, or (over 2^28 indices) packed into the work buffers for k_walk.  (0,1) zeros are
+    accepted (Definition 2.1); a bit at or above n makes the matrix invalid."""
+    ns, mats = mixed(20, 0, 20, 4040)
+    want = np.array(oracle_perms(mats), np.uint8)
+    flat = np.concatenate([P.perm_mod3_pack(M) for M in mats]).astype(np.uint64)
+    g = W.rng(4041)
+    r0 = 0
+    for k, n in enumerate(ns):
+        if k == 3 and n:
+            for r in range(n):                            # sgn set where mag is clear: still zeros
+                mag = int(flat[2 * (r0 + r)])
+                flat[2 * (r0 + r) + 1] |= np.uint64(int(g.integers(0, 1 << n)) & ~mag)
+        r0 += n
+    bad = flat.copy()
+    k7 = 7 if ns[7] else 8
+    row7 = int(np.sum(ns[:k7]))
+    bad[2 * row7] |= np.uint64(1) << np.uint64(ns[k7])      # a mag bit at column n
+    big_ns, big_mats = mixed(2, 28, 29, 4004)
+    big_want = np.array(oracle_perms(big_mats), np.uint8)
+    big_flat = np.concatenate([P.perm_mod3_pack(M) for M in big_mats]).astype(np.uint64)
+    for _ in range(2):
+        assert np.array_equal(run_packed(ns, flat), want)
+        got = run_packed(ns, bad)
+        for k in range(len(ns)):
+            assert got[k] == (P.PERM_RESULT_INVALID if k == k7 else want[k]), k
+        assert np.array_equal(run_packed(big_ns, big_flat), big_want)
+
+
 @pytest.mark.parametrize("states", [1, 2, 4])
 def test_states_per_lane(states):
     """The one-launch walk carries one chunk per lane whatever the tuning; the longer path (here a
@@ -136,5 +178,7 @@ def test_launch_counts():
         got, _ = run_dev([20], [A])
         assert got[0] == oracle.perm_mod3(A)
         assert P.timing_last().launches == 2               # device input: k_walk follows, with no tasks
+        run_packed([20], P.perm_mod3_pack(A).astype(np.uint64))
+        assert P.timing_last().launches == 2               # caller-packed planes: the same two launches
     finally:
         P.timing_enable(False)
