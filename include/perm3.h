@@ -240,7 +240,10 @@ typedef struct {
     uint64_t work_budget;   /* max admitted Gray indices still to visit (0 = none) */
     uint64_t quantum;       /* Gray indices per tick (0 = library default)         */
     int32_t  policy;        /* PERM_POLICY_*                                      */
-    int32_t  reserved;
+    int32_t  fast_max_n;    /* requests with n <= fast_max_n skip the slots and run
+                               in batches of up to 64 beside the tick in flight (one
+                               launch each); 0 = library default (18), -1 = none,
+                               else 1..22                                         */
 } perm_server_cfg;
 
 #define PERM_POLICY_SRPT 0   /* least remaining work first                         */

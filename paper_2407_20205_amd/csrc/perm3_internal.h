@@ -129,6 +129,7 @@ struct SmallAcc {
 };
 hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const PackPlanesArgs &pp, const SmallAcc &acc,
                         int kind, bool allow_fused, int blocks, hipStream_t st);
+uint64_t small_call_tasks(const PlanArgs &a, const int32_t *ns, int32_t count);
 hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st);
 hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st);
 hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st);

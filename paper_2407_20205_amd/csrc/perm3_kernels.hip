@@ -93,7 +93,7 @@ __device__ T block_incl_scan_1024(T v, T *sh, T &total)
     return r;
 }
 
-__device__ __forceinline__ void range_of(const PlanArgs &a, int n, uint64_t &lo, uint64_t &hi)
+__host__ __device__ __forceinline__ void range_of(const PlanArgs &a, int n, uint64_t &lo, uint64_t &hi)
 {
     if (a.use_range) {
         lo = a.range_lo;
@@ -106,7 +106,7 @@ __device__ __forceinline__ void range_of(const PlanArgs &a, int n, uint64_t &lo,
 
 // Chunk log that gives each persistent wave about tasks_per_wave tasks of the
 // whole call's work.
-__device__ __forceinline__ int target_chunk_log(const PlanArgs &a, double total_work)
+__host__ __device__ __forceinline__ int target_chunk_log(const PlanArgs &a, double total_work)
 {
     const double want_tasks = (double)a.waves_total * (double)(a.tasks_per_wave > 0 ? a.tasks_per_wave : 1);
     const double per_task = total_work / want_tasks;
@@ -117,7 +117,7 @@ __device__ __forceinline__ int target_chunk_log(const PlanArgs &a, double total_
 // The plan of a matrix of order n (invalid outside 0..63): its mode, chunk
 // log, block log, Gray range and task count; row_base is filled in later.
 // Pure: reads and writes no memory.
-__device__ MatMeta plan_pure(const PlanArgs &a, int n, int target_m)
+__host__ __device__ MatMeta plan_pure(const PlanArgs &a, int n, int target_m)
 {
     const bool valid = n >= 0 && n <= 63;
     MatMeta mt;
@@ -849,6 +849,26 @@ hipError_t launch_plan(const PlanArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, a);
     return hipGetLastError();
+}
+
+// The tasks k_small's one-launch walk makes of these orders: the same plan
+// (one chunk per lane), run on the host so that a caller who knows the
+// orders can size the grid to the work.
+uint64_t small_call_tasks(const PlanArgs &a, const int32_t *ns, int32_t count)
+{
+    PlanArgs pf = a;
+    pf.states_log = 0;
+    double total_work = 0.0;
+    for (int32_t k = 0; k < count; ++k) {
+        if (ns[k] < 0 || ns[k] > 63) continue;
+        uint64_t lo, hi;
+        range_of(pf, ns[k], lo, hi);
+        total_work += (double)(hi - lo);
+    }
+    const int target_m = target_chunk_log(pf, total_work);
+    uint64_t tasks = 0;
+    for (int32_t k = 0; k < count; ++k) tasks += plan_pure(pf, ns[k], target_m).ntasks;
+    return tasks;
 }
 
 hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const PackPlanesArgs &pp, const SmallAcc &acc,

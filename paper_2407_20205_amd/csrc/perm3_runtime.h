@@ -53,6 +53,7 @@ struct Launch {
     int32_t use_range;
     uint64_t range_lo, range_hi;
     int32_t fused_only;           // the caller knows the call is walked by k_small alone
+    int32_t small_blocks;         // k_small's grid when the caller knows the work (0: the full grid)
 };
 
 using GraphKey = std::tuple<int, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, int, int>;

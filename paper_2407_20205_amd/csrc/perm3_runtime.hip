@@ -316,7 +316,8 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
         sa.tally = (int64_t *)small_acc.p;
         sa.done = (uint64_t *)small_acc.p + SMALL_PLAN_MAX;
         if (timed && L.fused_only) HIP_TRY(hipEventRecord(ev_walk0, st));
-        HIP_TRY(launch_small(pa, pk, pp, sa, bytes ? 0 : 1, !L.use_range, std::max(grid_blocks(), L.count + 1), st));
+        const int blocks = L.small_blocks > 0 ? std::min(L.small_blocks, grid_blocks()) : grid_blocks();
+        HIP_TRY(launch_small(pa, pk, pp, sa, bytes ? 0 : 1, !L.use_range, std::max(blocks, L.count + 1), st));
         if (L.fused_only) {
             if (timed) {
                 HIP_TRY(hipEventRecord(ev_walk1, st));
@@ -465,6 +466,12 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     uint64_t work = 0;
     for (int32_t k = 0; k < count; ++k) work += 1ull << ns[k];
     L.fused_only = count <= SMALL_PLAN_MAX && !use_range && work <= SMALL_FUSED_WORK ? 1 : 0;
+    if (L.fused_only) {
+        // one wave per task (4 per block): blocks beyond the tasks would only start and leave
+        const PlanArgs pa = plan_args(nullptr, count, nullptr, nullptr);
+        const uint64_t tasks = small_call_tasks(pa, ns, count);
+        L.small_blocks = (int32_t)std::min<uint64_t>((tasks + 3) / 4, (uint64_t)grid_blocks());
+    }
     rc = run(L, st, false);
     if (rc) return rc;
     if (tally_host) HIP_TRY(hipMemcpyAsync(tally_host, tally.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));

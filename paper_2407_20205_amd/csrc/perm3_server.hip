@@ -14,6 +14,13 @@
 //      copies the finished results back and hands them to perm_server_poll.
 // Requests arriving while a tick runs join the next one, so large and small
 // jobs share the device instead of queueing behind each other.
+//
+// Small requests (n <= fast_max_n) skip the slots: while a tick is in flight
+// the worker takes them from the queue in batches of up to 64 and runs each
+// batch as one small host call of the library (planned, packed and walked by
+// one launch on the library's stream).  The tick's grid leaves one wave per
+// SIMD free, so such a batch runs beside the tick and finishes in tens of
+// microseconds instead of waiting for the next tick.
 #include <hip/hip_runtime.h>
 #include <time.h>
 
@@ -63,10 +70,15 @@ constexpr int SLOT_ROWS = 64;
 
 }  // namespace
 
+constexpr int FAST_DEFAULT_N = 18;   // fast_max_n = 0
+constexpr int FAST_MAX_N = 22;       // 64 requests of this order are 2^28 Gray indices: one launch
+
 struct perm_server {
     perm_server_cfg cfg{};
     perm_tuning tuning{};
     int device = 0, cus = 0;
+    int fast_n = -1;                  // requests with n <= fast_n take the fast lane
+    Context *ctx = nullptr;           // the library context the fast lane calls into
     hipStream_t stream = nullptr;
     hipEvent_t ev_tick = nullptr;
 
@@ -90,12 +102,18 @@ struct perm_server {
 
     std::vector<Slot> slots;
     std::vector<int> free_slots;
+    std::deque<Request> fast;          // fast-lane requests taken by the worker (worker only)
+    // the tick in flight
+    size_t tick_nt = 0;
+    uint32_t tick_nfin = 0;
+    std::vector<int> tick_fin;
     uint64_t admitted_work = 0;
     uint64_t seq = 0;
 
     std::mutex mu;                    // guards queue, done, stats, stop
     std::condition_variable cv_work, cv_done;
     std::deque<Request> queue;
+    std::deque<Request> fast_queue;   // submitted requests for the fast lane
     std::deque<perm_done> done;
     bool stop = false;
     int32_t fatal = PERM_OK;
@@ -105,8 +123,12 @@ struct perm_server {
     int32_t init();
     void release();
     void run();
-    int32_t tick(std::vector<perm_done> &finished);
+    int32_t tick_launch(bool &launched);
+    int32_t tick_complete(std::vector<perm_done> &finished);
     void admit(std::deque<Request> &incoming, std::vector<int> &to_pack);
+    void take_fast();
+    int32_t serve_fast();
+    void publish(std::vector<perm_done> &finished);
 };
 
 #define SRV_TRY(expr)                                        \
@@ -213,9 +235,68 @@ void perm_server::admit(std::deque<Request> &incoming, std::vector<int> &to_pack
     }
 }
 
-// Plan, launch and complete one tick.  Requests finishing in it are appended.
-int32_t perm_server::tick(std::vector<perm_done> &finished)
+// Take the submitted fast-lane requests (caller holds mu).
+void perm_server::take_fast()
 {
+    while (!fast_queue.empty()) {
+        fast.push_back(std::move(fast_queue.front()));
+        fast_queue.pop_front();
+    }
+}
+
+// Run up to 64 fast-lane requests as one host call into the library context
+// and publish their results at once.
+int32_t perm_server::serve_fast()
+{
+    const int32_t count = (int32_t)std::min<size_t>(fast.size(), SMALL_PLAN_MAX);
+    if (count == 0) return PERM_OK;
+    const uint64_t t_admit = now_ns();
+    std::vector<const uint8_t *> As(count);
+    std::vector<int32_t> ns(count);
+    std::vector<uint8_t> out(count);
+    for (int32_t k = 0; k < count; ++k) {
+        As[k] = fast[k].A.data();
+        ns[k] = fast[k].n;
+    }
+    int32_t rc;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        rc = ctx->run_host(As.data(), ns.data(), count, false, 0, 0, out.data(), nullptr);
+    }
+    if (rc) return rc;
+    const uint64_t t = now_ns();
+    std::vector<perm_done> finished(count);
+    for (int32_t k = 0; k < count; ++k) {
+        perm_done &d = finished[k];
+        memset(&d, 0, sizeof d);
+        d.tag = fast[k].tag;
+        d.status = PERM_OK;
+        d.n = fast[k].n;
+        d.result = out[k];
+        d.t_submit_ns = fast[k].t_submit;
+        d.t_admit_ns = t_admit;
+        d.t_done_ns = t;
+    }
+    fast.erase(fast.begin(), fast.begin() + count);
+    publish(finished);
+    return PERM_OK;
+}
+
+// Hand finished requests to perm_server_poll.
+void perm_server::publish(std::vector<perm_done> &finished)
+{
+    if (finished.empty()) return;
+    std::lock_guard<std::mutex> g(mu);
+    for (auto &d : finished) done.push_back(d);
+    stats.completed += finished.size();
+    finished.clear();
+    cv_done.notify_all();
+}
+
+// Plan and launch one tick (asynchronous; tick_complete waits for it).
+int32_t perm_server::tick_launch(bool &launched)
+{
+    launched = false;
     std::vector<int> order;
     for (int s = 0; s < (int)slots.size(); ++s)
         if (slots[s].used && slots[s].next_chunk < slots[s].nchunks) order.push_back(s);
@@ -276,7 +357,9 @@ int32_t perm_server::tick(std::vector<perm_done> &finished)
     ta.ntasks = d_counts;
     ta.tally = d_tally;
     ta.queue = d_counts + 2;
-    int blocks = cus * std::min(tuning.waves_per_simd, walk_resident_per_cu(0));
+    // with a fast lane, one wave per SIMD stays free for its launches
+    const int per_cu = std::min(tuning.waves_per_simd, walk_resident_per_cu(0));
+    int blocks = cus * (fast_n >= 1 && per_cu > 1 ? per_cu - 1 : per_cu);
     const int need = (int)((nt + 3) / 4);
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
@@ -291,15 +374,25 @@ int32_t perm_server::tick(std::vector<perm_done> &finished)
     SRV_TRY(launch_finish(fa, (int)nfin, stream));
     if (nfin) SRV_TRY(hipMemcpyAsync(h_fin_out, d_fin_out, nfin, hipMemcpyDeviceToHost, stream));
     SRV_TRY(hipEventRecord(ev_tick, stream));
+    tick_nt = nt;
+    tick_nfin = nfin;
+    tick_fin.swap(fin_slots);
+    launched = true;
+    return PERM_OK;
+}
+
+// Wait for the tick in flight; requests finishing in it are appended.
+int32_t perm_server::tick_complete(std::vector<perm_done> &finished)
+{
     SRV_TRY(hipEventSynchronize(ev_tick));
     const uint64_t t = now_ns();
     {
         std::lock_guard<std::mutex> g(mu);
         stats.ticks += 1;
-        for (size_t i = 0; i < nt; ++i) stats.tick_indices += (uint64_t)h_tasks[i].nchunks << h_tasks[i].m;
+        for (size_t i = 0; i < tick_nt; ++i) stats.tick_indices += (uint64_t)h_tasks[i].nchunks << h_tasks[i].m;
     }
-    for (uint32_t i = 0; i < nfin; ++i) {
-        const int s = fin_slots[i];
+    for (uint32_t i = 0; i < tick_nfin; ++i) {
+        const int s = tick_fin[i];
         Slot &sl = slots[s];
         perm_done d;
         memset(&d, 0, sizeof d);
@@ -330,8 +423,10 @@ void perm_server::run()
         {
             // admit straight from the submission queue, so queue_cap bounds the waiting requests
             std::unique_lock<std::mutex> g(mu);
-            const bool idle = free_slots.size() == slots.size();
-            if (idle && queue.empty() && !stop) cv_work.wait(g, [&] { return stop || !queue.empty(); });
+            const bool idle = free_slots.size() == slots.size() && fast.empty();
+            if (idle && queue.empty() && fast_queue.empty() && !stop)
+                cv_work.wait(g, [&] { return stop || !queue.empty() || !fast_queue.empty(); });
+            take_fast();
             admit(queue, to_pack);
             stopping = stop;
         }
@@ -354,10 +449,29 @@ void perm_server::run()
             if (e != hipSuccess) rc = hip_fail(e, "admit");
         }
         const bool active = free_slots.size() < slots.size();
+        bool launched = false;
         if (rc == PERM_OK && active) {
             if (!busy_start) busy_start = now_ns();
-            rc = tick(finished);
+            rc = tick_launch(launched);
         }
+        // the fast lane: small requests in batches, beside the tick in flight
+        while (rc == PERM_OK) {
+            if (!fast.empty()) {
+                rc = serve_fast();
+                continue;
+            }
+            if (!launched) break;
+            const hipError_t q = hipEventQuery(ev_tick);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) {
+                rc = hip_fail(q, "hipEventQuery");
+                break;
+            }
+            std::unique_lock<std::mutex> g(mu);
+            cv_work.wait_for(g, std::chrono::microseconds(20), [&] { return !fast_queue.empty(); });
+            take_fast();
+        }
+        if (rc == PERM_OK && launched) rc = tick_complete(finished);
         {
             std::lock_guard<std::mutex> g(mu);
             if (busy_start && (rc != PERM_OK || free_slots.size() == slots.size())) {
@@ -382,6 +496,10 @@ void perm_server::run()
                         fail(sl.req.tag, sl.req.n, sl.req.t_submit);
                         sl.used = false;
                     }
+                for (auto &r : fast) fail(r.tag, r.n, r.t_submit);
+                fast.clear();
+                for (auto &r : fast_queue) fail(r.tag, r.n, r.t_submit);
+                fast_queue.clear();
                 for (auto &r : queue) fail(r.tag, r.n, r.t_submit);
                 queue.clear();
                 stop = true;
@@ -391,10 +509,10 @@ void perm_server::run()
             int act = 0;
             for (auto &sl : slots) act += sl.used ? 1 : 0;
             stats.active_slots = act;
-            stats.queued = (int32_t)queue.size();
+            stats.queued = (int32_t)(queue.size() + fast_queue.size() + fast.size());
             if (!finished.empty() || rc != PERM_OK) cv_done.notify_all();
             finished.clear();
-            const bool drained = act == 0 && queue.empty();
+            const bool drained = act == 0 && queue.empty() && fast_queue.empty() && fast.empty();
             if ((stopping && drained) || rc != PERM_OK) {
                 cv_done.notify_all();
                 return;
@@ -409,13 +527,16 @@ int32_t perm_server_create(const perm_server_cfg *cfg, perm_server **out)
 {
     if (!cfg || !out) return set_error(PERM_EINVAL, "null pointer");
     if (cfg->max_slots < 1 || cfg->max_slots > 65536 || cfg->queue_cap < 1 || cfg->queue_cap > (1 << 24) ||
-        (cfg->policy != PERM_POLICY_SRPT && cfg->policy != PERM_POLICY_FIFO))
+        (cfg->policy != PERM_POLICY_SRPT && cfg->policy != PERM_POLICY_FIFO) || cfg->fast_max_n < -1 ||
+        cfg->fast_max_n > FAST_MAX_N)
         return set_error(PERM_EINVAL, "server configuration out of range");
     Context *c = nullptr;
     int32_t rc = get_context(&c);
     if (rc) return rc;
     perm_server *s = new perm_server();
     s->cfg = *cfg;
+    s->ctx = c;
+    s->fast_n = cfg->fast_max_n == 0 ? FAST_DEFAULT_N : cfg->fast_max_n;
     if (s->cfg.quantum == 0) s->cfg.quantum = 1ull << 33;
     {
         std::lock_guard<std::mutex> g(c->mu);
@@ -451,7 +572,7 @@ int32_t perm_server_submit(perm_server *s, const uint8_t *A, int32_t n, uint64_t
     {
         std::lock_guard<std::mutex> g(s->mu);
         if (s->stop) return set_error(PERM_ESTATE, "server is shutting down");
-        if ((int32_t)s->queue.size() >= s->cfg.queue_cap) return PERM_EAGAIN;
+        if ((int32_t)(s->queue.size() + s->fast_queue.size()) >= s->cfg.queue_cap) return PERM_EAGAIN;
         if (n == 0) {
             // the empty product needs no device work
             perm_done d;
@@ -465,7 +586,10 @@ int32_t perm_server_submit(perm_server *s, const uint8_t *A, int32_t n, uint64_t
             s->cv_done.notify_all();
             return PERM_OK;
         }
-        s->queue.push_back(std::move(r));
+        if (n <= s->fast_n)
+            s->fast_queue.push_back(std::move(r));
+        else
+            s->queue.push_back(std::move(r));
         s->stats.submitted += 1;
     }
     s->cv_work.notify_one();

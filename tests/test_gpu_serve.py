@@ -28,12 +28,24 @@ def drain(srv, want_count, timeout_s=120.0):
     return got
 
 
-@pytest.mark.parametrize("policy", [P.PERM_POLICY_SRPT, P.PERM_POLICY_FIFO])
-def test_server_mixed_stream_vs_oracle(policy):
+_WANT = {}
+
+
+def mixed_trace():
     tr = W.serve_trace(count=400, rate=1e9, seed=41, n_lo=0, n_hi=30)
-    flush_print("oracle on 400 requests, n in 0..30")
-    want = oracle_perms(tr.mats)
-    with P.Server(max_slots=64, work_budget=1 << 33, quantum=1 << 30, policy=policy) as srv:
+    if "mixed" not in _WANT:
+        flush_print("oracle on 400 requests, n in 0..30")
+        _WANT["mixed"] = oracle_perms(tr.mats)
+    return tr, _WANT["mixed"]
+
+
+@pytest.mark.parametrize("fast_max_n", [0, -1, 22])
+@pytest.mark.parametrize("policy", [P.PERM_POLICY_SRPT, P.PERM_POLICY_FIFO])
+def test_server_mixed_stream_vs_oracle(policy, fast_max_n):
+    """With the fast lane at its default (n <= 18), off, and at its widest (n <= 22)."""
+    tr, want = mixed_trace()
+    with P.Server(max_slots=64, work_budget=1 << 33, quantum=1 << 30, policy=policy,
+                  fast_max_n=fast_max_n) as srv:
         for k, M in enumerate(tr.mats):
             while not srv.submit(M, k):
                 time.sleep(0.001)
@@ -83,3 +95,32 @@ def test_server_queue_full_and_errors():
         got = drain(srv, accepted)
         r = P.perm_mod3(A)
         assert all(d.result == r for d in got.values())
+
+
+def test_fast_lane_runs_beside_a_tick():
+    """Small requests submitted while a 36x36 is being walked in ticks finish long before it,
+    with results equal to the oracle's; the big one's result is unchanged."""
+    g = W.rng(43)
+    big = W.single_36()
+    smalls = [g.integers(0, 3, (n, n), dtype=np.uint8) for n in g.integers(6, 19, 80)]
+    want = oracle_perms(smalls)
+    with P.Server(max_slots=8, quantum=1 << 30, fast_max_n=18) as srv:
+        assert srv.submit(big, 0)
+        time.sleep(0.002)                               # the ticks of the 36x36 are running
+        for k, M in enumerate(smalls):
+            assert srv.submit(M, 1 + k)
+        got = drain(srv, 1 + len(smalls))
+        st = srv.stats()
+    assert got[0].result == P.perm_mod3(big)
+    assert st.ticks > 1
+    for k in range(len(smalls)):
+        d = got[1 + k]
+        assert d.status == 0 and d.result == want[k], k
+        assert d.t_done_ns < got[0].t_done_ns, k         # not queued behind the big request
+
+
+def test_server_config_errors():
+    for bad in (-2, 23):
+        with pytest.raises(P.PermError) as e:
+            P.Server(max_slots=4, fast_max_n=bad)
+        assert e.value.code == P.PERM_EINVAL
