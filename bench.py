@@ -496,6 +496,10 @@ def bench_serve(P, W, torch, rate, count, batched_terms_per_s, quantum=1 << 33, 
         rate = 0.7 * batched_terms_per_s / ew
     tr = W.serve_trace(count=count, rate=rate)
     terms = float(sum((1 << int(n)) - 1 for n in tr.ns))
+    # untimed warm-up: a short replay of another trace, so that loading the server's kernels and
+    # first-use allocations are not counted in the measured tail
+    replay_server(P, W.serve_trace(count=max(count // 10, 1), rate=rate, seed=W.SEED_SERVE + 1),
+                  P.PERM_POLICY_SRPT, quantum)
     log(f"serve: {count} requests at {rate:.1f}/s, {terms:.3e} terms")
     lat, res, span, st = replay_server(P, tr, P.PERM_POLICY_SRPT, quantum)
     log(f"serve: continuous batching done in {span:.2f} s, p50 {pct(lat, 50):.3f} ms, p99 {pct(lat, 99):.3f} ms")

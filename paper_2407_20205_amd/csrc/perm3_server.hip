@@ -18,9 +18,9 @@
 // Small requests (n <= fast_max_n) skip the slots: while a tick is in flight
 // the worker takes them from the queue in batches of up to 64 and runs each
 // batch as one small host call of the library (planned, packed and walked by
-// one launch on the library's stream).  The tick's grid leaves one wave per
-// SIMD free, so such a batch runs beside the tick and finishes in tens of
-// microseconds instead of waiting for the next tick.
+// one launch on the library's stream).  The tick's grid leaves a block slot
+// free on a quarter of the CUs, so such a batch runs beside the tick and
+// finishes in tens of microseconds instead of waiting for the next tick.
 #include <hip/hip_runtime.h>
 #include <time.h>
 
@@ -357,9 +357,11 @@ int32_t perm_server::tick_launch(bool &launched)
     ta.ntasks = d_counts;
     ta.tally = d_tally;
     ta.queue = d_counts + 2;
-    // with a fast lane, one wave per SIMD stays free for its launches
+    // with a fast lane, one block slot on a quarter of the CUs stays free for
+    // its launches (about 3% of the tick's waves at 8 waves per SIMD)
     const int per_cu = std::min(tuning.waves_per_simd, walk_resident_per_cu(0));
-    int blocks = cus * (fast_n >= 1 && per_cu > 1 ? per_cu - 1 : per_cu);
+    int blocks = cus * per_cu;
+    if (fast_n >= 1 && blocks > cus / 4) blocks -= std::max(1, cus / 4);
     const int need = (int)((nt + 3) / 4);
     if (blocks > need) blocks = need;
     if (blocks < 1) blocks = 1;
