@@ -643,6 +643,9 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk,
                                                       int kind, int allow_fused)
 {
     static_assert(WALK_BLOCK == PACK_BLOCK, "one block shape for both roles");
+    // a small call is latency-bound: beside the waves of a long walk on the
+    // same SIMDs (a serving tick), these waves issue first
+    __builtin_amdgcn_s_setprio(3);
     __shared__ SmallLds lds[WALK_BLOCK / 64];
     const int lane = threadIdx.x & 63;
     const int count = a.count;
