@@ -241,9 +241,9 @@ typedef struct {
     uint64_t quantum;       /* Gray indices per tick (0 = library default)         */
     int32_t  policy;        /* PERM_POLICY_*                                      */
     int32_t  fast_max_n;    /* requests with n <= fast_max_n skip the slots and run
-                               in batches of up to 64 beside the tick in flight (one
-                               launch each); 0 = library default (18), -1 = none,
-                               else 1..22                                         */
+                               in batches of up to 64 (and 2^28 Gray indices) beside
+                               the tick in flight, one launch each; 0 = library
+                               default (28), -1 = none, else 1..28               */
 } perm_server_cfg;
 
 #define PERM_POLICY_SRPT 0   /* least remaining work first                         */

@@ -16,7 +16,8 @@
 // jobs share the device instead of queueing behind each other.
 //
 // Small requests (n <= fast_max_n) skip the slots: while a tick is in flight
-// the worker takes them from the queue in batches of up to 64 and runs each
+// the worker takes them from the queue in batches of up to 64 (and 2^28 Gray
+// indices) and runs each
 // batch as one small host call of the library (planned, packed and walked by
 // one launch on the library's stream).  The tick's grid leaves a block slot
 // free on a quarter of the CUs, so such a batch runs beside the tick and
@@ -70,8 +71,8 @@ constexpr int SLOT_ROWS = 64;
 
 }  // namespace
 
-constexpr int FAST_DEFAULT_N = 18;   // fast_max_n = 0
-constexpr int FAST_MAX_N = 22;       // 64 requests of this order are 2^28 Gray indices: one launch
+constexpr int FAST_DEFAULT_N = 28;   // fast_max_n = 0
+constexpr int FAST_MAX_N = 28;       // one request of this order is 2^28 Gray indices: one launch
 
 struct perm_server {
     perm_server_cfg cfg{};
@@ -244,11 +245,16 @@ void perm_server::take_fast()
     }
 }
 
-// Run up to 64 fast-lane requests as one host call into the library context
-// and publish their results at once.
+// Run fast-lane requests, up to 64 of them and 2^28 Gray indices in all (one
+// launch walks them), as one host call into the library context and publish
+// their results at once.
 int32_t perm_server::serve_fast()
 {
-    const int32_t count = (int32_t)std::min<size_t>(fast.size(), SMALL_PLAN_MAX);
+    int32_t count = 0;
+    uint64_t work = 0;
+    while (count < (int32_t)fast.size() && count < SMALL_PLAN_MAX &&
+           (count == 0 || work + (1ull << fast[count].n) <= SMALL_FUSED_WORK))
+        work += 1ull << fast[count++].n;
     if (count == 0) return PERM_OK;
     const uint64_t t_admit = now_ns();
     std::vector<const uint8_t *> As(count);

@@ -39,10 +39,10 @@ def mixed_trace():
     return tr, _WANT["mixed"]
 
 
-@pytest.mark.parametrize("fast_max_n", [0, -1, 22])
+@pytest.mark.parametrize("fast_max_n", [0, -1, 18, 24])
 @pytest.mark.parametrize("policy", [P.PERM_POLICY_SRPT, P.PERM_POLICY_FIFO])
 def test_server_mixed_stream_vs_oracle(policy, fast_max_n):
-    """With the fast lane at its default (n <= 18), off, and at its widest (n <= 22)."""
+    """With the fast lane at its default (its widest, n <= 28), off, and narrower."""
     tr, want = mixed_trace()
     with P.Server(max_slots=64, work_budget=1 << 33, quantum=1 << 30, policy=policy,
                   fast_max_n=fast_max_n) as srv:
@@ -120,7 +120,7 @@ def test_fast_lane_runs_beside_a_tick():
 
 
 def test_server_config_errors():
-    for bad in (-2, 23):
+    for bad in (-2, 29):
         with pytest.raises(P.PermError) as e:
             P.Server(max_slots=4, fast_max_n=bad)
         assert e.value.code == P.PERM_EINVAL
