@@ -122,10 +122,10 @@ hipError_t launch_plan(const PlanArgs &a, hipStream_t st);
 constexpr int SMALL_PLAN_MAX = 64;   // calls of up to this many matrices are planned (and packed) by k_small
 constexpr uint64_t SMALL_FUSED_WORK = 1ull << 28;   // ... and are walked in the same launch up to this many indices
 
-// Per-matrix accumulators of one-launch small calls: zero between calls.
+// Per-matrix accumulator words of one-launch small calls (completed tasks
+// and biased tally in one uint64 each): zero between calls.
 struct SmallAcc {
-    int64_t *tally;     // SMALL_PLAN_MAX entries
-    uint64_t *done;     // SMALL_PLAN_MAX entries
+    uint64_t *word;     // SMALL_PLAN_MAX entries
 };
 hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const PackPlanesArgs &pp, const SmallAcc &acc,
                         int kind, bool allow_fused, int blocks, hipStream_t st);

@@ -574,8 +574,8 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
 // tau = wave, wave + waves, ... in rank order, packs its task's matrix into
 // its own LDS (one coalesced read of the bytes) and walks it from there.  No
 // result of another kernel is waited on, so the chain of dependent memory
-// reads is short.  The per-matrix accumulators are left at zero by the wave
-// that completes each matrix, ready for the next call.  A larger call is
+// reads is short.  The per-matrix accumulator words are left at zero by the
+// wave that completes each matrix, ready for the next call.  A larger call is
 // planned and packed here into the work buffers, and k_walk follows.
 
 struct SmallLds {
@@ -734,14 +734,18 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk,
             bool last = m.ntasks == 1;
             long long T = sum;
             if (!last) {
-                if (sum != 0) atomicAdd((unsigned long long *)&acc.tally[k], (unsigned long long)(long long)sum);
-                __threadfence();
-                const uint64_t prev = atomicAdd((unsigned long long *)&acc.done[k], 1ull);
-                if (prev + 1 == m.ntasks) {
-                    __threadfence();
-                    T = __hip_atomic_load((long long *)&acc.tally[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store((long long *)&acc.tally[k], 0ll, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    __hip_atomic_store((unsigned long long *)&acc.done[k], 0ull, __ATOMIC_RELAXED,
+                // one word per matrix: completed tasks from bit 40 up, and below
+                // them the tally plus a bias of 64 * 2^m per task (a task's sum
+                // is at least minus its index count, so no addend is negative;
+                // the biased total stays under 2^31 because the call walks at
+                // most 2^28 indices); one atomic per task, and the wave that
+                // completes the matrix reads its total from the returned value
+                const uint64_t bias = 64ull << m.m;
+                const uint64_t add = (1ull << 40) + (uint64_t)((long long)sum + (long long)bias);
+                const uint64_t now = atomicAdd((unsigned long long *)&acc.word[k], (unsigned long long)add) + add;
+                if ((now >> 40) == m.ntasks) {
+                    T = (long long)(now & ((1ull << 40) - 1)) - (long long)(m.ntasks * bias);
+                    __hip_atomic_store((unsigned long long *)&acc.word[k], 0ull, __ATOMIC_RELAXED,
                                        __HIP_MEMORY_SCOPE_AGENT);
                     last = true;
                 }

@@ -69,7 +69,7 @@ struct Context {
 
     DevBuf meta, order, task_start, tally, done, status, counters, rowbuf;
     DevBuf d_stage, d_census, d_gen, d_wide;
-    DevBuf small_acc;                // SmallAcc: 2 x SMALL_PLAN_MAX words, zero between calls
+    DevBuf small_acc;                // SmallAcc: SMALL_PLAN_MAX words, zero between calls
     HostBuf h_stage, h_wide;
     HostBuf h_out;                   // host-call results, written by the kernels directly
 

@@ -184,8 +184,8 @@ int32_t get_context(Context **out)
     HIP_TRY(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
-    HIP_TRY(c->small_acc.reserve(2 * SMALL_PLAN_MAX * sizeof(uint64_t)));
-    HIP_TRY(hipMemset(c->small_acc.p, 0, 2 * SMALL_PLAN_MAX * sizeof(uint64_t)));
+    HIP_TRY(c->small_acc.reserve(SMALL_PLAN_MAX * sizeof(uint64_t)));
+    HIP_TRY(hipMemset(c->small_acc.p, 0, SMALL_PLAN_MAX * sizeof(uint64_t)));
     *out = c.get();
     g_ctx[dev] = std::move(c);
     return PERM_OK;
@@ -313,8 +313,7 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
     if (small) {
         // one launch plans and packs and, for little work, walks too
         SmallAcc sa;
-        sa.tally = (int64_t *)small_acc.p;
-        sa.done = (uint64_t *)small_acc.p + SMALL_PLAN_MAX;
+        sa.word = (uint64_t *)small_acc.p;
         if (timed && L.fused_only) HIP_TRY(hipEventRecord(ev_walk0, st));
         const int blocks = L.small_blocks > 0 ? std::min(L.small_blocks, grid_blocks()) : grid_blocks();
         HIP_TRY(launch_small(pa, pk, pp, sa, bytes ? 0 : 1, !L.use_range, std::max(blocks, L.count + 1), st));
