@@ -9,8 +9,9 @@
 //                  (Steele, Lea and Flood, 2014): state s_q = key + q * 0x9E3779B97F4A7C15,
 //                  output = mix(s_q) (uniform random matrices, Table 4).
 //
-// k_census_lanes: one matrix per lane for n <= CENSUS_LANE_MAX_N.  The lane
-// walks all 2^n - 1 Gray steps of its matrix with every index tested (the
+// k_census_lanes: one matrix at a time per lane for n <= CENSUS_LANE_MAX_N,
+// each lane over a run of consecutive matrices.  The lane walks all 2^n - 1
+// Gray steps of its matrix with every index tested (the
 // rows sit in LDS, one column of words per lane; all lanes flip the same row
 // at the same step), forms ((-1)^n T) mod 3, and the wave counts results 0,
 // 1 and 2 with ballots.  Larger n: k_generate writes the matrices and the
@@ -23,12 +24,19 @@
 
 namespace perm3 {
 
-__device__ __forceinline__ uint64_t splitmix_out(uint64_t key, uint64_t q)
+constexpr uint64_t SPLITMIX_GAMMA = 0x9E3779B97F4A7C15ull;
+
+// SplitMix64's output function of state z
+__device__ __forceinline__ uint64_t splitmix_mix(uint64_t z)
 {
-    uint64_t z = key + q * 0x9E3779B97F4A7C15ull;
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t splitmix_out(uint64_t key, uint64_t q)
+{
+    return splitmix_mix(key + q * SPLITMIX_GAMMA);
 }
 
 // floor(3 x / 2^64): the high word of 3x = 2x + x
@@ -62,26 +70,65 @@ __global__ void __launch_bounds__(CENSUS_BLOCK) k_census_lanes(CensusArgs a)
     const int nn = n * n;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    // each lane takes a run of consecutive matrices: after the first, the next
+    // matrix comes from the last by a base-3 increment of its entries
+    // (enumeration) or by carrying on with the generator's state (SplitMix64)
     const uint64_t lanes = (uint64_t)gridDim.x * CENSUS_BLOCK;
-    const uint64_t rounds = (a.count + lanes - 1) / lanes;
+    const uint64_t per = (a.count + lanes - 1) / lanes;
+    const uint64_t begin = ((uint64_t)blockIdx.x * CENSUS_BLOCK + tid) * per;
     const uint32_t mask = (1u << n) - 1u;
     unsigned long long c0 = 0, c1 = 0, c2 = 0;
-    for (uint64_t r = 0; r < rounds; ++r) {
-        const uint64_t idx = r * lanes + (uint64_t)blockIdx.x * CENSUS_BLOCK + tid;
+    uint64_t x = 0;   // SplitMix64 state of the lane's next entry
+    for (uint64_t r = 0; r < per; ++r) {
+        const uint64_t idx = begin + r;
         const bool active = idx < a.count;
-        const uint64_t t = a.first + idx;
-        // the lane's matrix, packed by phi: element j of row i at bit n-1-j
-        uint64_t rest = t;
-        for (int i = 0; i < n; ++i) {
-            uint32_t mag = 0, sgn = 0;
-            for (int j = 0; j < n; ++j) {
-                const uint32_t v = census_entry(a.gen, a.key, t, nn, i * n + j, rest);
-                const uint32_t bit = 1u << (n - 1 - j);
-                mag |= v != 0 ? bit : 0u;
-                sgn |= v == 2 ? bit : 0u;
+        if (active && (r == 0 || a.gen != GEN_ENUMERATE)) {
+            // the matrix from scratch, packed by phi: element j of row i at bit n-1-j
+            const uint64_t t = a.first + idx;
+            uint64_t rest = t;
+            if (r == 0) x = a.key + (t * (uint64_t)nn + 1u) * SPLITMIX_GAMMA;
+            for (int i = 0; i < n; ++i) {
+                uint32_t mag = 0, sgn = 0;
+                for (int j = 0; j < n; ++j) {
+                    uint32_t v;
+                    if (a.gen == GEN_ENUMERATE) {
+                        const uint64_t q = rest / 3u;
+                        v = (uint32_t)(rest - 3u * q);
+                        rest = q;
+                    } else {
+                        v = trit_of(splitmix_mix(x));
+                        x += SPLITMIX_GAMMA;
+                    }
+                    const uint32_t bit = 1u << (n - 1 - j);
+                    mag |= v != 0 ? bit : 0u;
+                    sgn |= v == 2 ? bit : 0u;
+                }
+                s_m[i][tid] = mag;
+                s_s[i][tid] = sgn;
             }
-            s_m[i][tid] = mag;
-            s_s[i][tid] = sgn;
+        } else if (active) {
+            // t = t_prev + 1: add 1 to the base-3 number whose digit k is entry k
+            // (row-major); a digit 2 (-1) becomes 0 and carries
+            for (int i = 0; i < n; ++i) {
+                uint32_t m = s_m[i][tid], sg = s_s[i][tid];
+                bool carry = true;
+                for (int j = 0; j < n && carry; ++j) {
+                    const uint32_t bit = 1u << (n - 1 - j);
+                    if (!(m & bit)) {
+                        m |= bit;                  // 0 -> 1
+                        carry = false;
+                    } else if (!(sg & bit)) {
+                        sg |= bit;                 // 1 -> 2
+                        carry = false;
+                    } else {
+                        m &= ~bit;                 // 2 -> 0
+                        sg &= ~bit;
+                    }
+                }
+                s_m[i][tid] = m;
+                s_s[i][tid] = sg;
+                if (!carry) break;
+            }
         }
         // Gray walk over all subsets from the empty one: every index tested
         uint32_t ml = 0, sl = 0;
