@@ -61,12 +61,88 @@ __device__ __forceinline__ uint32_t census_entry(int gen, uint64_t key, uint64_t
 }
 
 constexpr int CENSUS_BLOCK = 256;
+constexpr int CENSUS_UL = 4;   // the lane walk's blocks are 2^4 Gray steps
+
+// The lanes' rows in LDS, sized to the call's n: row i of lane tid's matrix
+// at [i * CENSUS_BLOCK + tid] (mag words, then the sgn words after n rows).
+#define CROW(a, i) (a)[(i) * CENSUS_BLOCK + tid]
+
+// The Ryser tally T of the lane's matrix: the Gray walk over all subsets from
+// the empty one, every index tested.
+__device__ int census_walk_plain(int n, uint32_t mask, int tid, const uint32_t *s_m, const uint32_t *s_s)
+{
+    uint32_t ml = 0, sl = 0;
+    int tally = 0;
+    const uint32_t steps = (1u << n) - 1u;
+    for (uint32_t i = 1; i <= steps; ++i) {
+        const int tr = __builtin_ctz(i);
+        const uint32_t rm = CROW(s_m, tr), rs0 = CROW(s_s, tr);
+        const bool leave = (i >> (tr + 1)) & 1u;
+        bip_add(ml, sl, rm, leave ? (rs0 ^ rm) : rs0);
+        if (ml == mask) {
+            const int par = (__builtin_popcount(sl) + (int)(i & 1u)) & 1;
+            tally += par ? -1 : 1;
+        }
+    }
+    return tally;
+}
+
+// The same walk for n > CENSUS_UL in unrolled blocks of 16 steps: the rows
+// flipped inside a block (0..3) sit in VGPRs, the row of the step closing the
+// block is read from LDS once per block, and every index is still tested,
+// without branches (small n makes hits far too common to skip blocks).
+__device__ int census_walk_blocks(int n, uint32_t mask, int tid, const uint32_t *s_m, const uint32_t *s_s)
+{
+    constexpr int U = 1 << CENSUS_UL;
+    uint32_t vm[CENSUS_UL], vs[CENSUS_UL], vsn[CENSUS_UL];
+#pragma unroll
+    for (int t = 0; t < CENSUS_UL; ++t) {
+        vm[t] = CROW(s_m, t);
+        vs[t] = CROW(s_s, t);
+        vsn[t] = vs[t] ^ vm[t];
+    }
+    const uint32_t nblocks = 1u << (n - CENSUS_UL);
+    uint32_t ml = 0, sl = 0;
+    int tally = 0;
+    for (uint32_t b = 0; b < nblocks; ++b) {
+        // the step closing block b enters index 16 (b + 1); the last block has none
+        const uint32_t jb = b + 1;
+        const bool closing = jb < nblocks;
+        const int tb = closing ? CENSUS_UL + __builtin_ctz(jb) : 0;   // a row of the matrix either way
+        const int sh = closing ? tb - CENSUS_UL + 1 : 0;
+        const bool leave_b = closing && ((jb >> sh) & 1u);
+        const uint32_t bm = closing ? CROW(s_m, tb) : 0u;
+        const uint32_t bs0 = closing ? CROW(s_s, tb) : 0u;
+        const uint32_t bs = leave_b ? (bs0 ^ bm) : bs0;
+#pragma unroll
+        for (int k = 1; k <= U; ++k) {
+            uint32_t rm, rs;
+            if (k < U) {
+                const int t = __builtin_ctz(k);
+                rm = vm[t];
+                // the step into 16 b + k leaves the subset when bit t+1 of the index is set
+                const bool leave = t + 1 < CENSUS_UL ? ((k >> (t + 1)) & 1) != 0 : (b & 1u) != 0;
+                rs = leave ? vsn[t] : vs[t];
+            } else {
+                rm = bm;
+                rs = bs;
+            }
+            bip_add(ml, sl, rm, rs);
+            // the index 16 b + k has the parity of k
+            const int odd = (__builtin_popcount(sl) + k) & 1;
+            const int term = odd ? -1 : 1;
+            const bool exists = k < U || closing;   // the last block ends at index 2^n - 1
+            tally += exists && ml == mask ? term : 0;
+        }
+    }
+    return tally;
+}
 
 __global__ void __launch_bounds__(CENSUS_BLOCK) k_census_lanes(CensusArgs a)
 {
-    __shared__ uint32_t s_m[CENSUS_LANE_MAX_N][CENSUS_BLOCK];
-    __shared__ uint32_t s_s[CENSUS_LANE_MAX_N][CENSUS_BLOCK];
+    extern __shared__ uint32_t s_rows[];
     const int n = a.n;
+    uint32_t *s_m = s_rows, *s_s = s_rows + n * CENSUS_BLOCK;
     const int nn = n * n;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -103,14 +179,14 @@ __global__ void __launch_bounds__(CENSUS_BLOCK) k_census_lanes(CensusArgs a)
                     mag |= v != 0 ? bit : 0u;
                     sgn |= v == 2 ? bit : 0u;
                 }
-                s_m[i][tid] = mag;
-                s_s[i][tid] = sgn;
+                CROW(s_m, i) = mag;
+                CROW(s_s, i) = sgn;
             }
         } else if (active) {
             // t = t_prev + 1: add 1 to the base-3 number whose digit k is entry k
             // (row-major); a digit 2 (-1) becomes 0 and carries
             for (int i = 0; i < n; ++i) {
-                uint32_t m = s_m[i][tid], sg = s_s[i][tid];
+                uint32_t m = CROW(s_m, i), sg = CROW(s_s, i);
                 bool carry = true;
                 for (int j = 0; j < n && carry; ++j) {
                     const uint32_t bit = 1u << (n - 1 - j);
@@ -125,25 +201,12 @@ __global__ void __launch_bounds__(CENSUS_BLOCK) k_census_lanes(CensusArgs a)
                         sg &= ~bit;
                     }
                 }
-                s_m[i][tid] = m;
-                s_s[i][tid] = sg;
+                CROW(s_m, i) = m;
+                CROW(s_s, i) = sg;
                 if (!carry) break;
             }
         }
-        // Gray walk over all subsets from the empty one: every index tested
-        uint32_t ml = 0, sl = 0;
-        int tally = 0;
-        const uint32_t steps = (1u << n) - 1u;
-        for (uint32_t i = 1; i <= steps; ++i) {
-            const int tr = __builtin_ctz(i);
-            const uint32_t rm = s_m[tr][tid], rs0 = s_s[tr][tid];
-            const bool leave = (i >> (tr + 1)) & 1u;
-            bip_add(ml, sl, rm, leave ? (rs0 ^ rm) : rs0);
-            if (ml == mask) {
-                const int par = (__builtin_popcount(sl) + (int)(i & 1u)) & 1;
-                tally += par ? -1 : 1;
-            }
-        }
+        const int tally = n > CENSUS_UL ? census_walk_blocks(n, mask, tid, s_m, s_s) : census_walk_plain(n, mask, tid, s_m, s_s);
         const int p = (n & 1) ? -tally : tally;
         int res = p % 3;
         if (res < 0) res += 3;
@@ -180,7 +243,8 @@ __global__ void __launch_bounds__(256) k_generate(GenArgs a)
 hipError_t launch_census_lanes(const CensusArgs &a, int grid_blocks, hipStream_t st)
 {
     if (a.n < 1 || a.n > CENSUS_LANE_MAX_N) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_census_lanes, dim3(grid_blocks), dim3(CENSUS_BLOCK), 0, st, a);
+    const size_t lds = 2u * (size_t)a.n * CENSUS_BLOCK * sizeof(uint32_t);   // at most 40 KiB
+    hipLaunchKernelGGL(k_census_lanes, dim3(grid_blocks), dim3(CENSUS_BLOCK), lds, st, a);
     return hipGetLastError();
 }
 
