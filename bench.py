@@ -396,6 +396,28 @@ def bench_pi50(P, W, shards=64, ckdir=None):
     return out
 
 
+# ------------------------------------------------------------------ exact census (Section 4, Table 3)
+
+def read_table3():
+    with open(os.path.join(ROOT, "tests", "golden", "table3_zero_counts.txt")) as f:
+        return [tuple(int(x) for x in line.split()) for line in f if line.strip() and not line.startswith("#")]
+
+
+def bench_census(P):
+    """Table 3's exact counts: every n x n matrix over F_3 (n = 1..5) enumerated on the device."""
+    out = {"rows": []}
+    for n, z_paper in read_table3():
+        total = 3 ** (n * n)
+        t0 = time.perf_counter()
+        c = P.perm_mod3_census(n, P.PERM_GEN_ENUMERATE, 0, 0, total)
+        sec = time.perf_counter() - t0
+        out["rows"].append({"n": n, "matrices": total, "z": c[0], "ones": c[1], "minus_ones": c[2],
+                            "z_table3": z_paper, "equal": c[0] == z_paper, "seconds": sec,
+                            "matrices_per_s": total / sec})
+        log(f"z({n}) = {c[0]} (Table 3: {z_paper}), {total} matrices in {sec:.2f} s")
+    return out
+
+
 # ------------------------------------------------------------------ Monte Carlo (Section 4, Table 4)
 
 def read_table4():
@@ -552,7 +574,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--only", choices=["headline", "single20", "batch", "serve", "large", "wide", "vec", "pi50",
-                                       "montecarlo"],
+                                       "montecarlo", "census"],
                     default=None)
     ap.add_argument("--mc-scale", type=float, default=0.01, help="fraction of Table 4's trial counts")
     ap.add_argument("--mc-n", default="6-30", help="range of n for the Monte Carlo study, e.g. 6-17")
@@ -638,6 +660,8 @@ def main():
     if args.only == "montecarlo":
         lo, hi = (int(x) for x in args.mc_n.split("-"))
         line["montecarlo"] = bench_montecarlo(P, args.mc_scale, lo, hi)
+    if args.only == "census":
+        line["census"] = bench_census(P)
     if args.only == "pi50":
         line["pi50"] = bench_pi50(P, W, ckdir=args.checkpoint_dir)
     if args.only is None and not args.no_cpu:
