@@ -15,13 +15,14 @@
 // Requests arriving while a tick runs join the next one, so large and small
 // jobs share the device instead of queueing behind each other.
 //
-// Small requests (n <= fast_max_n) skip the slots: while a tick is in flight
-// the worker takes them from the queue in batches of up to 64 (and 2^28 Gray
-// indices) and runs each
-// batch as one small host call of the library (planned, packed and walked by
-// one launch on the library's stream).  The tick's grid leaves a block slot
-// free on a quarter of the CUs, so such a batch runs beside the tick and
-// finishes in tens of microseconds instead of waiting for the next tick.
+// Small requests (n <= fast_max_n) skip the slots: they wait in a queue of
+// their own, and while a tick is in flight (or when none is) the worker takes
+// them in batches of up to 64 requests and 2^28 Gray indices and runs each
+// batch as one small host call of the library: planned, packed and walked by
+// one launch on the library's stream, whose waves raise their issue priority.
+// The tick's grid leaves a block slot free on a quarter of the CUs, so such a
+// batch runs beside the tick and finishes in tens of microseconds instead of
+// waiting for the next tick.
 #include <hip/hip_runtime.h>
 #include <time.h>
 
