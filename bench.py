@@ -22,6 +22,15 @@ import time
 
 import numpy as np
 
+
+def input_sha256(*arrays) -> str:
+    """SHA-256 of the generated uint8 matrices, in order, so any run can be matched to the oracle's inputs."""
+    import hashlib
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a, dtype=np.uint8).tobytes())
+    return h.hexdigest()
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -103,7 +112,9 @@ def bench_headline(P, W, torch, steps, warmup):
         "terms_per_s": steps * terms / sec,
         "ms_per_step": 1e3 * sec / steps,
         "hot_kernel_ms_mean": float(np.mean(hot)),
+        "hot_kernel_ms_median": float(np.median(hot)),
         "hot_kernel_ms_min": float(np.min(hot)),
+        "input_sha256": input_sha256(A),
         "launches_ms_mean": float(np.mean(total)),
         "result": result,
         "roofline": {
@@ -167,6 +178,7 @@ def bench_batch(P, W, torch, reps, baseline=True):
         "ms_per_batch": 1e3 * sec,
         "hist_per_n": per_n,
         "zero_fraction": float(np.mean(res == 0)),
+        "input_sha256": input_sha256(*b.mats),
     }
     if not baseline:
         return result
@@ -229,6 +241,7 @@ def bench_single20(P, W, torch, reps=200):
                         "synchronised each call",
             "p50_us": 1e6 * pct(lat, 50), "p99_us": 1e6 * pct(lat, 99),
             "terms_per_s": ((1 << 20) - 1) / pct(lat, 50), "result": int(out.item()),
+            "input_sha256": input_sha256(A),
             "host_call": {"workload": "perm_mod3(A, 20) from host memory, result to host",
                           "p50_us": 1e6 * pct(hl, 50), "p99_us": 1e6 * pct(hl, 99), "result": int(r)}}
 
@@ -262,6 +275,7 @@ def bench_large(P, W, torch):
     terms44 = (1 << 44) - 1
     terms40 = sp.count * ((1 << 40) - 1)
     return {"workload": "one 44x44 uniform matrix; 64 matrices 40x40 with P(0)=0.6, P(1)=P(2)=0.2",
+            "input_sha256": input_sha256(big, *sp.mats),
             "n44_s": t44, "n44_terms_per_s": terms44 / t44, "n44_result": r44,
             "sparse40_s": t40, "sparse40_terms_per_s": terms40 / t40,
             "sparse40_matrices_per_s": sp.count / t40,
@@ -539,6 +553,7 @@ def bench_serve(P, W, torch, rate, count, batched_terms_per_s, quantum=1 << 33, 
         "terms_per_s": terms / span,
         "ticks": int(st.ticks),
         "quantum": quantum,
+        "input_sha256": input_sha256(*tr.mats),
         "baseline_fifo_one_launch_per_request": {"p50_ms": pct(blat, 50), "p99_ms": pct(blat, 99),
                                                  "requests_per_s": count / bspan},
         "results_identical_to_baseline": bool(res == bres),
@@ -560,7 +575,20 @@ def bench_cpu(W, seconds=12.0):
     t0 = time.perf_counter()
     oracle.range_tally(A, a, a + length, threads=threads)
     sec = time.perf_counter() - t0
+    # one core, over a short range of the same matrix
+    one = 1 << 24
+    t0 = time.perf_counter()
+    oracle.range_tally(A, a, a + one, threads=1)
+    one_s = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((line.split(":", 1)[1].strip() for line in f if line.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": length / sec, "unit": "subset-terms/s", "cores": threads, "kind": "oracle",
+            "single_core_terms_per_s": one / one_s, "cpu_model": model, "os_cpu_count": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
             "sample": f"Gray indices [{a}, {a + length}) of the 36x36 matrix ({length} of 2^36 terms), "
                       f"{sec:.1f} s on {threads} threads; full matrix extrapolates to "
                       f"{(1 << 36) / (length / sec):.0f} s"}
