@@ -32,7 +32,9 @@ struct DevBuf {
 struct HostBuf {   // pinned host memory
     void *p = nullptr;
     size_t cap = 0;
+    unsigned flags = hipHostMallocDefault;
     HostBuf() = default;
+    explicit HostBuf(unsigned f) : flags(f) {}
     HostBuf(const HostBuf &) = delete;
     HostBuf &operator=(const HostBuf &) = delete;
     ~HostBuf();
@@ -72,6 +74,7 @@ struct Context {
     DevBuf small_acc;                // SmallAcc: SMALL_PLAN_MAX words, zero between calls
     HostBuf h_stage, h_wide;
     HostBuf h_out;                   // host-call results, written by the kernels directly
+    HostBuf h_zc{hipHostMallocCoherent};   // small host calls' inputs, read by the kernel directly
 
     std::map<GraphKey, hipGraphExec_t> graphs;
     hipEvent_t ev_walk0 = nullptr, ev_walk1 = nullptr, ev_all0 = nullptr, ev_all1 = nullptr;

@@ -130,7 +130,7 @@ hipError_t HostBuf::reserve(size_t n)
         cap = 0;
     }
     size_t want = std::max<size_t>(n, 4096);
-    hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(&p, want, flags);
     if (e == hipSuccess) cap = want;
     return e;
 }
@@ -424,15 +424,32 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     const size_t offs_at = (((size_t)bytes + 15) / 16) * 16;
     const size_t ns_at = offs_at + offs_bytes;
     const size_t stage_bytes = ns_at + ns_bytes;
-    HIP_TRY(h_stage.reserve(stage_bytes));
-    HIP_TRY(d_stage.reserve(stage_bytes));
+    // the orders are known here: a small call whose walk k_small takes alone
+    // needs no k_walk after it (the kernel makes the same decision)
+    uint64_t work = 0;
+    int32_t nmax = 0;
+    for (int32_t k = 0; k < count; ++k) {
+        work += 1ull << ns[k];
+        nmax = std::max(nmax, ns[k]);
+    }
+    const bool fused_only = count <= SMALL_PLAN_MAX && !use_range && work <= SMALL_FUSED_WORK;
+    uint64_t tasks = 0;
+    if (fused_only) tasks = small_call_tasks(plan_args(nullptr, count, nullptr, nullptr), ns, count);
+    // Such a call reads its inputs straight from coherent pinned memory when
+    // that moves little over the host link (each of its waves reads the
+    // orders, the offsets and its matrix once): no staging copy before it.
+    const bool zero_copy =
+        fused_only && tasks * (uint64_t)(12 * count + nmax * nmax) <= (1ull << 20);
+    HostBuf &hst = zero_copy ? h_zc : h_stage;
+    HIP_TRY(hst.reserve(stage_bytes));
+    if (!zero_copy) HIP_TRY(d_stage.reserve(stage_bytes));
     // results go straight to pinned host memory: no copy after the walk
     HIP_TRY(h_out.reserve((size_t)std::max(count, 1)));
     uint8_t *out_dev = nullptr;
     HIP_TRY(hipHostGetDevicePointer((void **)&out_dev, h_out.p, 0));
     int32_t rc = reserve_work(count, rows);
     if (rc) return rc;
-    uint8_t *h = (uint8_t *)h_stage.p;
+    uint8_t *h = (uint8_t *)hst.p;
     int64_t *hoffs = (int64_t *)(h + offs_at);
     int32_t *hns = (int32_t *)(h + ns_at);
     int64_t o = 0;
@@ -446,8 +463,13 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     hipStream_t st = stream;
     rc = join(st);
     if (rc) return rc;
-    HIP_TRY(hipMemcpyAsync(d_stage.p, h_stage.p, stage_bytes, hipMemcpyHostToDevice, st));
-    uint8_t *d = (uint8_t *)d_stage.p;
+    uint8_t *d = nullptr;
+    if (zero_copy) {
+        HIP_TRY(hipHostGetDevicePointer((void **)&d, hst.p, 0));
+    } else {
+        HIP_TRY(hipMemcpyAsync(d_stage.p, h_stage.p, stage_bytes, hipMemcpyHostToDevice, st));
+        d = (uint8_t *)d_stage.p;
+    }
     Launch L;
     memset(&L, 0, sizeof L);
     L.pack_kind = 0;
@@ -460,17 +482,9 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     L.use_range = use_range ? 1 : 0;
     L.range_lo = lo;
     L.range_hi = hi;
-    // the orders are known here: a small call whose walk k_small takes alone
-    // needs no k_walk after it (the kernel makes the same decision)
-    uint64_t work = 0;
-    for (int32_t k = 0; k < count; ++k) work += 1ull << ns[k];
-    L.fused_only = count <= SMALL_PLAN_MAX && !use_range && work <= SMALL_FUSED_WORK ? 1 : 0;
-    if (L.fused_only) {
-        // one wave per task (4 per block): blocks beyond the tasks would only start and leave
-        const PlanArgs pa = plan_args(nullptr, count, nullptr, nullptr);
-        const uint64_t tasks = small_call_tasks(pa, ns, count);
-        L.small_blocks = (int32_t)std::min<uint64_t>((tasks + 3) / 4, (uint64_t)grid_blocks());
-    }
+    L.fused_only = fused_only ? 1 : 0;
+    // one wave per task (4 per block): blocks beyond the tasks would only start and leave
+    if (fused_only) L.small_blocks = (int32_t)std::min<uint64_t>((tasks + 3) / 4, (uint64_t)grid_blocks());
     rc = run(L, st, false);
     if (rc) return rc;
     if (tally_host) HIP_TRY(hipMemcpyAsync(tally_host, tally.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
