@@ -132,6 +132,12 @@ def range_tally(A, a: int, b: int, threads: int | None = None) -> int:
     return int(v)
 
 
+def perm_from_tally(n: int, T: int) -> int:
+    """perm(A) mod 3 in {0, 1, 2} from the whole Gray sum T = T(0, 2^n): eq. (2) carries the
+    factor (-1)^n outside the sum over subsets."""
+    return (-T if n % 2 else T) % 3
+
+
 def perm_mod3(A, threads: int | None = None) -> int:
     """perm(A) mod 3 in {0, 1, 2} through Ryser + Gray code on unpacked residues."""
     A, n = _mat(A)
