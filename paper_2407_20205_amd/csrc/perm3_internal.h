@@ -4,52 +4,11 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "perm3_plan.hpp"
+
 namespace perm3 {
 
 struct RowW;
-
-enum WalkMode : int32_t {
-    MODE_FAST = 0,     // unrolled fast walk over whole chunks, exact replay of candidate blocks
-    MODE_DIRECT = 1,   // every index tested exactly (small n)
-    MODE_NONE = 2,     // no tasks: n == 0, invalid n, or an empty range
-};
-
-// Per-matrix plan, written by the plan kernel.
-struct MatMeta {
-    int32_t n;
-    int32_t m;          // log2 of the per-lane chunk length
-    int32_t mode;       // WalkMode
-    int32_t ul;         // log2 of the unrolled block (4, 5 or 6)
-    uint64_t ntasks;    // 64 * S chunks per task
-    int64_t row_base;   // first RowW of this matrix
-    uint64_t lo, hi;    // Gray index range [lo, hi)
-    uint64_t c_first;   // first chunk index (lo >> m)
-};
-
-// counters[] slots
-enum : int { CNT_QUEUE = 0, CNT_TOTAL_TASKS = 1, CNT_COUNT = 4 };
-
-struct PlanArgs {
-    const int32_t *ns;
-    int32_t count;
-    int32_t use_range;            // 1: matrix 0 walks [range_lo, range_hi) only (count == 1)
-    uint64_t range_lo, range_hi;
-    int32_t body_log, chunk_log_max, direct_max_n, direct_chunk_log_max;
-    int32_t body_log_mid, mid_max_n;  // block length for direct_max_n < n <= mid_max_n
-    int32_t states_log;           // log2 of the chunks a lane carries side by side
-    int32_t max_tasks_log;        // at most 2^max_tasks_log tasks per matrix ...
-    int32_t min_task_log;         // ... unless tasks would exceed 2^min_task_log indices
-    int32_t waves_total, tasks_per_wave;
-    MatMeta *meta;
-    int32_t *order;               // [count] matrix index by decreasing n
-    uint64_t *task_start;         // [count + 1] first task of order[p]
-    int64_t *tally;               // [count]
-    uint64_t *done;               // [count]
-    uint8_t *status;              // [count] 0 ok, 1 invalid
-    uint64_t *counters;           // [CNT_COUNT]
-    uint8_t *out;                 // [count]
-    uint64_t *hist;               // [64 * 3] or null
-};
 
 struct PackU8Args {
     const uint8_t *mats;
@@ -119,8 +78,6 @@ struct FinishArgs {
 };
 
 hipError_t launch_plan(const PlanArgs &a, hipStream_t st);
-constexpr int SMALL_PLAN_MAX = 64;   // calls of up to this many matrices are planned (and packed) by k_small
-constexpr uint64_t SMALL_FUSED_WORK = 1ull << 28;   // ... and are walked in the same launch up to this many indices
 
 // Per-matrix accumulator words of one-launch small calls (completed tasks
 // and biased tally in one uint64 each): zero between calls.
@@ -129,7 +86,6 @@ struct SmallAcc {
 };
 hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const PackPlanesArgs &pp, const SmallAcc &acc,
                         int kind, bool allow_fused, int blocks, hipStream_t st);
-uint64_t small_call_tasks(const PlanArgs &a, const int32_t *ns, int32_t count);
 hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st);
 hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st);
 hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st);
@@ -137,6 +93,8 @@ hipError_t launch_tick(const TickArgs &a, int grid_blocks, hipStream_t st);
 int walk_resident_per_cu(int states);   // k_walk<states> workgroups per CU at once; 0: k_tick
 hipError_t launch_finish(const FinishArgs &a, int max_fin, hipStream_t st);
 hipError_t launch_slot_pack(const uint8_t *A, int n, RowW *dst, hipStream_t st);
+hipError_t launch_finish_tallies(const int64_t *t, int32_t count, int32_t n, uint8_t *out, hipStream_t st);
+hipError_t launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t st);
 hipError_t launch_bipedal_ops(const uint32_t *in, int count, uint32_t *out, hipStream_t st);
 
 constexpr int WALK_BLOCK = 256;   // 4 waves, one per SIMD

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <atomic>
 
 #include "perm3_device.hpp"
@@ -91,89 +92,6 @@ __device__ T block_incl_scan_1024(T v, T *sh, T &total)
     const T r = sh[tid];
     __syncthreads();
     return r;
-}
-
-__host__ __device__ __forceinline__ void range_of(const PlanArgs &a, int n, uint64_t &lo, uint64_t &hi)
-{
-    if (a.use_range) {
-        lo = a.range_lo;
-        hi = a.range_hi;
-    } else {
-        lo = 0;
-        hi = 1ull << n;
-    }
-}
-
-// Chunk log that gives each persistent wave about tasks_per_wave tasks of the
-// whole call's work.
-__host__ __device__ __forceinline__ int target_chunk_log(const PlanArgs &a, double total_work)
-{
-    const double want_tasks = (double)a.waves_total * (double)(a.tasks_per_wave > 0 ? a.tasks_per_wave : 1);
-    const double per_task = total_work / want_tasks;
-    if (per_task < 128.0) return 0;
-    return (63 - __builtin_clzll((uint64_t)per_task)) - 6 - a.states_log;
-}
-
-// The plan of a matrix of order n (invalid outside 0..63): its mode, chunk
-// log, block log, Gray range and task count; row_base is filled in later.
-// Pure: reads and writes no memory.
-__host__ __device__ MatMeta plan_pure(const PlanArgs &a, int n, int target_m)
-{
-    const bool valid = n >= 0 && n <= 63;
-    MatMeta mt;
-    mt.n = valid ? n : 0;
-    mt.m = 0;
-    mt.mode = MODE_NONE;
-    mt.ntasks = 0;
-    mt.row_base = 0;
-    mt.lo = 0;
-    mt.hi = 0;
-    mt.c_first = 0;
-    mt.ul = a.body_log;
-    if (!valid || n == 0) return mt;
-    uint64_t lo, hi;
-    range_of(a, n, lo, hi);
-    mt.lo = lo;
-    mt.hi = hi;
-    const int slog = a.states_log;
-    const int ul = n <= a.mid_max_n ? a.body_log_mid : a.body_log;
-    mt.ul = ul;
-    const bool fast_ok = n >= ul + 7 + slog && n > a.direct_max_n;
-    int m;
-    if (fast_ok) {
-        // a lane's int32 tally covers S chunks and a wave sums 64 lanes: S * 2^m <= 2^24
-        int mmax = a.chunk_log_max < n - 6 - slog ? a.chunk_log_max : n - 6 - slog;
-        if (mmax > 24 - slog) mmax = 24 - slog;
-        // at most 2^max_tasks_log tasks for this matrix, and at most about
-        // 2^(n/2) for a small one (a task's fixed cost, its seed and its
-        // cold start, then outweighs the walk it shares out), unless its
-        // tasks would then exceed 2^min_task_log indices: every task ends
-        // with an atomic on the matrix's counters, and those serialise
-        const int tasks_log = (n - 3) / 2 < a.max_tasks_log ? (n - 3) / 2 : a.max_tasks_log;
-        const int fewer = n - 6 - slog - tasks_log;
-        const int longest = a.min_task_log - 6 - slog;
-        const int mfloor = fewer < longest ? fewer : longest;
-        m = target_m > mfloor ? target_m : mfloor;
-        if (m > mmax) m = mmax;
-        if (m < ul + 1) m = ul + 1;
-        mt.mode = MODE_FAST;
-    } else {
-        m = n - 6;
-        if (m > a.direct_chunk_log_max) m = a.direct_chunk_log_max;
-        if (m < 0) m = 0;
-        mt.mode = MODE_DIRECT;
-    }
-    mt.m = m;
-    if (hi > lo) {
-        const uint64_t c0 = lo >> m;
-        const uint64_t c1 = (hi - 1) >> m;
-        mt.c_first = c0;
-        const uint64_t per_task = 64ull << a.states_log;
-        mt.ntasks = (c1 - c0 + per_task) / per_task;
-    } else {
-        mt.mode = MODE_NONE;
-    }
-    return mt;
 }
 
 // The plan of matrix k with its side effects: clears the matrix's tally and
@@ -824,6 +742,17 @@ __global__ void __launch_bounds__(64) k_slot_pack(const uint8_t *A, int n, RowW 
     store_row(dst + r, mag, sgn);
 }
 
+// ((-1)^n times the sum of the tallies) mod 3: eq. (2) finished over pieces
+// of the Gray range walked separately (Section 3.1), for example the shards
+// of a long run.  One wavefront.
+__global__ void __launch_bounds__(64) k_finish_tallies(const int64_t *t, int32_t count, int32_t n, uint8_t *out)
+{
+    long long s = 0;
+    for (int32_t i = threadIdx.x; i < count; i += 64) s += t[i];
+    s = wave_sum_i64(s);
+    if (threadIdx.x == 0) *out = finish_mod3(n, s);
+}
+
 // ------------------------------------------------------------------ self-check
 
 // Theorem 2.1 on individual 32-bit words, through the same device functions
@@ -850,32 +779,20 @@ __global__ void k_bipedal_ops(const uint32_t *in, int count, uint32_t *out)
     out[8 * i + 7] = ns;
 }
 
+// p[0 .. count) = value: clears counters and accumulator words with a kernel,
+// which a stream capture records as a kernel node.
+__global__ void k_fill_u64(uint64_t *p, int64_t count, uint64_t value)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
 // ------------------------------------------------------------------ launchers
 
 hipError_t launch_plan(const PlanArgs &a, hipStream_t st)
 {
     hipLaunchKernelGGL(k_plan, dim3(1), dim3(1024), 0, st, a);
     return hipGetLastError();
-}
-
-// The tasks k_small's one-launch walk makes of these orders: the same plan
-// (one chunk per lane), run on the host so that a caller who knows the
-// orders can size the grid to the work.
-uint64_t small_call_tasks(const PlanArgs &a, const int32_t *ns, int32_t count)
-{
-    PlanArgs pf = a;
-    pf.states_log = 0;
-    double total_work = 0.0;
-    for (int32_t k = 0; k < count; ++k) {
-        if (ns[k] < 0 || ns[k] > 63) continue;
-        uint64_t lo, hi;
-        range_of(pf, ns[k], lo, hi);
-        total_work += (double)(hi - lo);
-    }
-    const int target_m = target_chunk_log(pf, total_work);
-    uint64_t tasks = 0;
-    for (int32_t k = 0; k < count; ++k) tasks += plan_pure(pf, ns[k], target_m).ntasks;
-    return tasks;
 }
 
 hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const PackPlanesArgs &pp, const SmallAcc &acc,
@@ -953,6 +870,20 @@ hipError_t launch_finish(const FinishArgs &a, int max_fin, hipStream_t st)
 hipError_t launch_slot_pack(const uint8_t *A, int n, RowW *dst, hipStream_t st)
 {
     hipLaunchKernelGGL(k_slot_pack, dim3(1), dim3(64), 0, st, A, n, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_tallies(const int64_t *t, int32_t count, int32_t n, uint8_t *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finish_tallies, dim3(1), dim3(64), 0, st, t, count, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(uint64_t *p, int64_t count, uint64_t value, hipStream_t st)
+{
+    if (count <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((count + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, st, p, count, value);
     return hipGetLastError();
 }
 
