@@ -172,6 +172,16 @@ int32_t perm_mod3_batch(const uint8_t *const *As, const int32_t *ns, int32_t cou
  * into a HIP graph and replayed afterwards.  Calls into one device are
  * ordered among themselves, whatever their streams.  Buffers must stay valid
  * until the stream reaches the call's end.
+ *
+ * Graph capture: a call made while the caller captures `stream` (a non-NULL
+ * stream, for example inside torch.cuda.graph) records its kernels into the
+ * caller's graph and returns; nothing runs until the graph is launched.  Such
+ * a call gets device work buffers of its own (allocated at capture time, kept
+ * until the process ends), so every replay recomputes it from whatever the
+ * input buffers then hold, and replays are not ordered with other calls into
+ * the library: they need not be, since they share no buffers with them.  The
+ * graph holds no memset node.  The first call on a device may be a captured
+ * one.
  */
 int32_t perm_mod3_batch_dev(const uint8_t *mats_dev, const int64_t *offs_dev,
                              const int32_t *ns_dev, int32_t count, uint8_t *out_dev,
@@ -189,6 +199,22 @@ int32_t perm_mod3_batch_dev(const uint8_t *mats_dev, const int64_t *offs_dev,
 int32_t perm_mod3_batch_packed(const uint64_t *planes_dev, const int64_t *row_off_dev,
                                 const int32_t *ns_dev, int32_t count, uint8_t *out_dev,
                                 uint64_t *hist_dev, void *stream);
+
+/*
+ * perm_mod3_from_tallies: perm(A) mod 3 of an n x n matrix from the exact
+ * partial tallies T(a_k, b_k) of Gray ranges that together cover [0, 2^n)
+ * exactly once (for example the shards of a long run, each from
+ * perm_mod3_range_tally, possibly on different devices): by eq. (2) and the
+ * additivity of T over blocks of consecutive Gray states (Section 3.1),
+ * perm(A) = (-1)^n * sum_k T_k, reduced here mod 3 on the device.
+ *   tallies: host int64[count], 1 <= count <= PERM_MAX_TALLIES; their true
+ *            sum must fit in int64 (it does for tallies of such a cover).
+ *   *out:    host byte in {0,1,2}.
+ * Synchronous.  PERM_EINVAL for n outside [0, 63], count out of range or a
+ * null pointer.
+ */
+#define PERM_MAX_TALLIES (1 << 20)
+int32_t perm_mod3_from_tallies(int32_t n, const int64_t *tallies, int32_t count, uint8_t *out);
 
 /*
  * perm_mod3_pack: the map phi of Section 2 applied to each row of A on the host:
@@ -332,8 +358,11 @@ int32_t perm_device_info_get(perm_device_info *info);
 
 /* Device self-check of Theorem 2.1: for each of the count inputs
  * in[4k..4k+3] = (mag1, sgn1, mag2, sgn2) (32-bit words), writes
- * out[8k..8k+7] = (mag,sgn) of +, -, x, / as computed by the device functions
- * the kernels use.  in/out: host.  For testing. */
+ * out[8k..8k+7] = (mag, sgn) of, in order: the sum by the printed addition
+ * formula, the difference by the printed subtraction formula, the product,
+ * and the difference as the walk forms it (the sum with the negated second
+ * operand, whose sgn word is sgn2 xor mag2), each computed by the device
+ * functions the kernels use.  in/out: host.  For testing. */
 int32_t perm_bipedal_ops(const uint32_t *in, int32_t count, uint32_t *out);
 
 const char *perm_strerror(int32_t code);

@@ -5,8 +5,10 @@
 #include <stdint.h>
 
 #include <map>
+#include <memory>
 #include <mutex>
 #include <tuple>
+#include <vector>
 
 #include "perm3.h"
 #include "perm3_internal.h"
@@ -41,6 +43,27 @@ struct HostBuf {   // pinned host memory
     hipError_t reserve(size_t n);
 };
 
+// Device work buffers of one call: plan records, packed rows, tallies,
+// completion counts, status, the queue counters, and the accumulator words of
+// one-launch small calls (SMALL_PLAN_MAX of them, zero between calls).
+struct WorkSet {
+    MatMeta *meta = nullptr;
+    int32_t *order = nullptr;
+    uint64_t *task_start = nullptr;   // count + 1
+    int64_t *tally = nullptr;
+    uint64_t *done = nullptr;
+    uint8_t *status = nullptr;
+    uint64_t *counters = nullptr;     // CNT_COUNT
+    RowW *rows = nullptr;
+    uint64_t *acc = nullptr;          // SMALL_PLAN_MAX
+};
+
+// Bytes of a work set for `count` matrices and `rows` rows in all (with the
+// accumulator words when `acc`), and its buffers carved from one block of at
+// least that many bytes (256-byte aligned pieces).
+size_t workset_bytes(int32_t count, int64_t rows, bool acc);
+WorkSet workset_carve(void *base, int32_t count, int64_t rows, bool acc);
+
 // One device launch sequence: plan -> pack -> walk.
 struct Launch {
     int32_t pack_kind;            // 0: byte matrices, 1: uint64 planes
@@ -56,6 +79,7 @@ struct Launch {
     uint64_t range_lo, range_hi;
     int32_t fused_only;           // the caller knows the call is walked by k_small alone
     int32_t small_blocks;         // k_small's grid when the caller knows the work (0: the full grid)
+    int32_t zero_acc;             // clear the accumulator words first (a set not known to hold zeros)
 };
 
 using GraphKey = std::tuple<int, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, int, int>;
@@ -69,9 +93,13 @@ struct Context {
     hipStream_t stream = nullptr;
     std::mutex mu;
 
-    DevBuf meta, order, task_start, tally, done, status, counters, rowbuf;
+    DevBuf work;                     // the shared work set (grown on demand)
     DevBuf d_stage, d_census, d_gen, d_wide;
-    DevBuf small_acc;                // SmallAcc: SMALL_PLAN_MAX words, zero between calls
+    DevBuf small_acc;                // its accumulator words: SMALL_PLAN_MAX, zero between calls
+    WorkSet ws{};
+    int32_t ws_count = 0;
+    int64_t ws_rows = 0;
+    std::vector<std::unique_ptr<DevBuf>> captured;   // work sets of calls captured into callers' graphs
     HostBuf h_stage, h_wide;
     HostBuf h_out;                   // host-call results, written by the kernels directly
     HostBuf h_zc{hipHostMallocCoherent};   // small host calls' inputs, read by the kernel directly
@@ -86,15 +114,17 @@ struct Context {
     int last_graph = 0;
 
     ~Context();
-    int waves_total() const;
-    int grid_blocks() const;
+    int grid_blocks() const { return grid_blocks(tuning); }
     void drop_graphs();
     int32_t reserve_work(int32_t count, int64_t rows);
     int32_t join(hipStream_t st);
     int32_t mark(hipStream_t st);
-    PlanArgs plan_args(const int32_t *ns_dev, int32_t count, uint8_t *out_dev, uint64_t *hist_dev);
-    WalkArgs walk_args(int32_t count, uint8_t *out_dev, uint64_t *hist_dev);
-    int32_t enqueue(const Launch &L, hipStream_t st, bool timed);
+    PlanArgs plan_args(const WorkSet &w, const perm_tuning &tn, const int32_t *ns_dev, int32_t count,
+                       uint8_t *out_dev, uint64_t *hist_dev) const;
+    WalkArgs walk_args(const WorkSet &w, int32_t count, uint8_t *out_dev, uint64_t *hist_dev) const;
+    int grid_blocks(const perm_tuning &tn) const;
+    int32_t enqueue(const Launch &L, const WorkSet &w, const perm_tuning &tn, hipStream_t st, bool timed);
+    int32_t run_captured(const Launch &L, hipStream_t st);
     int32_t run(const Launch &L, hipStream_t st, bool use_graph);
     int32_t run_dev(const Launch &L, hipStream_t user);
     int32_t run_host(const uint8_t *const *As, const int32_t *ns, int32_t count, bool use_range, uint64_t lo,

@@ -135,6 +135,46 @@ hipError_t HostBuf::reserve(size_t n)
     return e;
 }
 
+static constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// The pieces of a work set, in order, each 256-byte aligned.
+struct WorkSetLayout {
+    size_t off[10];
+};
+
+static constexpr WorkSetLayout workset_layout(int32_t count, int64_t rows, bool acc)
+{
+    const size_t c = (size_t)(count > 1 ? count : 1);
+    const size_t r = (size_t)(rows > 1 ? rows : 1);
+    const size_t sz[9] = {c * sizeof(MatMeta), c * sizeof(int32_t), (c + 1) * sizeof(uint64_t),
+                          c * sizeof(int64_t), c * sizeof(uint64_t), c, CNT_COUNT * sizeof(uint64_t),
+                          r * sizeof(RowW), acc ? SMALL_PLAN_MAX * sizeof(uint64_t) : 0};
+    WorkSetLayout L{};
+    L.off[0] = 0;
+    for (int i = 0; i < 9; ++i) L.off[i + 1] = L.off[i] + align256(sz[i]);
+    return L;
+}
+
+size_t workset_bytes(int32_t count, int64_t rows, bool acc) { return workset_layout(count, rows, acc).off[9]; }
+
+WorkSet workset_carve(void *base, int32_t count, int64_t rows, bool acc)
+{
+    const WorkSetLayout L = workset_layout(count, rows, acc);
+    const size_t *off = L.off;
+    uint8_t *b = (uint8_t *)base;
+    WorkSet w;
+    w.meta = (MatMeta *)(b + off[0]);
+    w.order = (int32_t *)(b + off[1]);
+    w.task_start = (uint64_t *)(b + off[2]);
+    w.tally = (int64_t *)(b + off[3]);
+    w.done = (uint64_t *)(b + off[4]);
+    w.status = b + off[5];
+    w.counters = (uint64_t *)(b + off[6]);
+    w.rows = (RowW *)(b + off[7]);
+    w.acc = acc ? (uint64_t *)(b + off[8]) : nullptr;
+    return w;
+}
+
 Context::~Context()
 {
     for (auto &kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -153,6 +193,9 @@ static std::mutex g_ctx_mu;
 static std::map<int, std::unique_ptr<Context>> g_ctx;
 static thread_local bool tl_timing = false;
 
+// The context of the current device, made on first use.  Making one creates
+// a stream and events and allocates no device memory: work buffers come with
+// the first call that needs them.
 int32_t get_context(Context **out)
 {
     int dev = 0;
@@ -184,8 +227,6 @@ int32_t get_context(Context **out)
     HIP_TRY(hipEventCreateWithFlags(&c->ev_done, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
-    HIP_TRY(c->small_acc.reserve(SMALL_PLAN_MAX * sizeof(uint64_t)));
-    HIP_TRY(hipMemset(c->small_acc.p, 0, SMALL_PLAN_MAX * sizeof(uint64_t)));
     *out = c.get();
     g_ctx[dev] = std::move(c);
     return PERM_OK;
@@ -195,11 +236,10 @@ bool timing_enabled() { return tl_timing; }
 
 // The persistent walk's workgroups (4 waves each, one per SIMD): waves_per_simd
 // per CU, but no more than fit on a CU at once.
-int Context::grid_blocks() const
+int Context::grid_blocks(const perm_tuning &tn) const
 {
-    return cus * std::min(tuning.waves_per_simd, walk_resident_per_cu(tuning.states_per_lane));
+    return cus * std::min(tn.waves_per_simd, walk_resident_per_cu(tn.states_per_lane));
 }
-int Context::waves_total() const { return 4 * grid_blocks(); }
 
 void Context::drop_graphs()
 {
@@ -207,21 +247,25 @@ void Context::drop_graphs()
     graphs.clear();
 }
 
-// Make sure the work buffers hold `count` matrices with `rows` rows in total.
+// Make sure the shared work set holds `count` matrices with `rows` rows in total.
 int32_t Context::reserve_work(int32_t count, int64_t rows)
 {
-    const size_t c = (size_t)std::max(count, 1);
-    void *before[8] = {meta.p, order.p, task_start.p, tally.p, done.p, status.p, counters.p, rowbuf.p};
-    HIP_TRY(meta.reserve(c * sizeof(MatMeta)));
-    HIP_TRY(order.reserve(c * sizeof(int32_t)));
-    HIP_TRY(task_start.reserve((c + 1) * sizeof(uint64_t)));
-    HIP_TRY(tally.reserve(c * sizeof(int64_t)));
-    HIP_TRY(done.reserve(c * sizeof(uint64_t)));
-    HIP_TRY(status.reserve(c));
-    HIP_TRY(counters.reserve(CNT_COUNT * sizeof(uint64_t)));
-    HIP_TRY(rowbuf.reserve((size_t)std::max<int64_t>(rows, 1) * sizeof(RowW)));
-    void *after[8] = {meta.p, order.p, task_start.p, tally.p, done.p, status.p, counters.p, rowbuf.p};
-    if (memcmp(before, after, sizeof before) != 0) drop_graphs();
+    if (!small_acc.p) {
+        HIP_TRY(small_acc.reserve(SMALL_PLAN_MAX * sizeof(uint64_t)));
+        HIP_TRY(hipMemset(small_acc.p, 0, SMALL_PLAN_MAX * sizeof(uint64_t)));
+    }
+    count = std::max(count, 1);
+    rows = std::max<int64_t>(rows, 1);
+    if (work.p && count <= ws_count && rows <= ws_rows) return PERM_OK;
+    const int32_t c = std::max(count, ws_count);
+    const int64_t r = std::max(rows, ws_rows);
+    void *before = work.p;
+    HIP_TRY(work.reserve(workset_bytes(c, r, false)));
+    ws = workset_carve(work.p, c, r, false);
+    ws.acc = (uint64_t *)small_acc.p;
+    ws_count = c;
+    ws_rows = r;
+    if (work.p != before) drop_graphs();
     return PERM_OK;
 }
 
@@ -240,56 +284,57 @@ int32_t Context::mark(hipStream_t st)
     return PERM_OK;
 }
 
-PlanArgs Context::plan_args(const int32_t *ns_dev, int32_t count, uint8_t *out_dev, uint64_t *hist_dev)
+PlanArgs Context::plan_args(const WorkSet &w, const perm_tuning &tn, const int32_t *ns_dev, int32_t count,
+                            uint8_t *out_dev, uint64_t *hist_dev) const
 {
     PlanArgs a;
     memset(&a, 0, sizeof a);
     a.ns = ns_dev;
     a.count = count;
-    a.body_log = tuning.body_log;
-    a.chunk_log_max = tuning.chunk_log_max;
-    a.direct_max_n = tuning.direct_max_n;
+    a.body_log = tn.body_log;
+    a.chunk_log_max = tn.chunk_log_max;
+    a.direct_max_n = tn.direct_max_n;
     a.direct_chunk_log_max = 10;
-    a.body_log_mid = tuning.body_log_mid;
-    a.mid_max_n = tuning.mid_max_n;
-    a.states_log = tuning.states_per_lane == 4 ? 2 : (tuning.states_per_lane == 2 ? 1 : 0);
-    a.max_tasks_log = tuning.max_tasks_log;
-    a.min_task_log = tuning.min_task_log;
-    a.waves_total = waves_total();
-    a.tasks_per_wave = tuning.tasks_per_wave;
-    a.meta = (MatMeta *)meta.p;
-    a.order = (int32_t *)order.p;
-    a.task_start = (uint64_t *)task_start.p;
-    a.tally = (int64_t *)tally.p;
-    a.done = (uint64_t *)done.p;
-    a.status = (uint8_t *)status.p;
-    a.counters = (uint64_t *)counters.p;
+    a.body_log_mid = tn.body_log_mid;
+    a.mid_max_n = tn.mid_max_n;
+    a.states_log = tn.states_per_lane == 4 ? 2 : (tn.states_per_lane == 2 ? 1 : 0);
+    a.max_tasks_log = tn.max_tasks_log;
+    a.min_task_log = tn.min_task_log;
+    a.waves_total = 4 * grid_blocks(tn);
+    a.tasks_per_wave = tn.tasks_per_wave;
+    a.meta = w.meta;
+    a.order = w.order;
+    a.task_start = w.task_start;
+    a.tally = w.tally;
+    a.done = w.done;
+    a.status = w.status;
+    a.counters = w.counters;
     a.out = out_dev;
     a.hist = hist_dev;
     return a;
 }
 
-WalkArgs Context::walk_args(int32_t count, uint8_t *out_dev, uint64_t *hist_dev)
+WalkArgs Context::walk_args(const WorkSet &w, int32_t count, uint8_t *out_dev, uint64_t *hist_dev) const
 {
-    WalkArgs w;
-    w.rows = (const RowW *)rowbuf.p;
-    w.meta = (const MatMeta *)meta.p;
-    w.order = (const int32_t *)order.p;
-    w.task_start = (const uint64_t *)task_start.p;
-    w.count = count;
-    w.tally = (int64_t *)tally.p;
-    w.done = (uint64_t *)done.p;
-    w.status = (const uint8_t *)status.p;
-    w.counters = (uint64_t *)counters.p;
-    w.out = out_dev;
-    w.hist = hist_dev;
-    return w;
+    WalkArgs a;
+    a.rows = w.rows;
+    a.meta = w.meta;
+    a.order = w.order;
+    a.task_start = w.task_start;
+    a.count = count;
+    a.tally = w.tally;
+    a.done = w.done;
+    a.status = w.status;
+    a.counters = w.counters;
+    a.out = out_dev;
+    a.hist = hist_dev;
+    return a;
 }
 
-// Enqueue plan -> pack -> walk.  pack_kind: 0 bytes, 1 planes.
-int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
+// Enqueue plan -> pack -> walk on the work set w.  pack_kind: 0 bytes, 1 planes.
+int32_t Context::enqueue(const Launch &L, const WorkSet &w, const perm_tuning &tn, hipStream_t st, bool timed)
 {
-    PlanArgs pa = plan_args(L.ns_dev, L.count, L.out_dev, L.hist_dev);
+    PlanArgs pa = plan_args(w, tn, L.ns_dev, L.count, L.out_dev, L.hist_dev);
     pa.use_range = L.use_range;
     pa.range_lo = L.range_lo;
     pa.range_hi = L.range_hi;
@@ -297,25 +342,27 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
     PackU8Args pk;
     pk.mats = L.mats_dev;
     pk.offs = L.offs_dev;
-    pk.meta = (const MatMeta *)meta.p;
+    pk.meta = w.meta;
     pk.count = L.count;
-    pk.rows = (RowW *)rowbuf.p;
-    pk.status = (uint8_t *)status.p;
+    pk.rows = w.rows;
+    pk.status = w.status;
     PackPlanesArgs pp;
     pp.planes = L.planes_dev;
     pp.row_off = L.row_off_dev;
-    pp.meta = (const MatMeta *)meta.p;
+    pp.meta = w.meta;
     pp.count = L.count;
-    pp.rows = (RowW *)rowbuf.p;
-    pp.status = (uint8_t *)status.p;
+    pp.rows = w.rows;
+    pp.status = w.status;
     const bool small = L.count <= SMALL_PLAN_MAX;
     const bool bytes = L.pack_kind == 0;
+    const int grid = grid_blocks(tn);
     if (small) {
         // one launch plans and packs and, for little work, walks too
         SmallAcc sa;
-        sa.word = (uint64_t *)small_acc.p;
+        sa.word = w.acc;
+        if (L.zero_acc) HIP_TRY(launch_fill_u64(w.acc, SMALL_PLAN_MAX, 0, st));
         if (timed && L.fused_only) HIP_TRY(hipEventRecord(ev_walk0, st));
-        const int blocks = L.small_blocks > 0 ? std::min(L.small_blocks, grid_blocks()) : grid_blocks();
+        const int blocks = L.small_blocks > 0 ? std::min(L.small_blocks, grid) : grid;
         HIP_TRY(launch_small(pa, pk, pp, sa, bytes ? 0 : 1, !L.use_range, std::max(blocks, L.count + 1), st));
         if (L.fused_only) {
             if (timed) {
@@ -323,7 +370,7 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
                 HIP_TRY(hipEventRecord(ev_all1, st));
             }
             last_timing_valid = timed;
-            last_launches = 1;
+            last_launches = L.zero_acc ? 2 : 1;
             return PERM_OK;
         }
     } else {
@@ -331,13 +378,13 @@ int32_t Context::enqueue(const Launch &L, hipStream_t st, bool timed)
         HIP_TRY(bytes ? launch_pack_u8(pk, st) : launch_pack_planes(pp, st));
     }
     if (timed) HIP_TRY(hipEventRecord(ev_walk0, st));
-    HIP_TRY(launch_walk(walk_args(L.count, L.out_dev, L.hist_dev), tuning.states_per_lane, grid_blocks(), st));
+    HIP_TRY(launch_walk(walk_args(w, L.count, L.out_dev, L.hist_dev), tn.states_per_lane, grid, st));
     if (timed) {
         HIP_TRY(hipEventRecord(ev_walk1, st));
         HIP_TRY(hipEventRecord(ev_all1, st));
     }
     last_timing_valid = timed;
-    last_launches = small ? 2 : 3;
+    last_launches = (small ? 2 : 3) + (L.zero_acc ? 1 : 0);
     return PERM_OK;
 }
 
@@ -351,7 +398,7 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
     // Calls of up to SMALL_PLAN_MAX matrices are two launches, issued directly:
     // replaying them as a graph costs more than it saves.
     if (timed || !use_graph || !tuning.use_graphs || L.count <= SMALL_PLAN_MAX) {
-        rc = enqueue(L, st, timed);
+        rc = enqueue(L, ws, tuning, st, timed);
         if (rc) return rc;
         return mark(st);
     }
@@ -369,7 +416,7 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
         if (graphs.size() >= 32) drop_graphs();
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        rc = enqueue(L, st, false);
+        rc = enqueue(L, ws, tuning, st, false);
         hipError_t e = hipStreamEndCapture(st, &g);
         if (rc) {
             if (g) (void)hipGraphDestroy(g);
@@ -388,6 +435,33 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
     last_timing_valid = false;
     last_launches = 3;   // graphs are used for calls of more than SMALL_PLAN_MAX matrices only
     return mark(st);
+}
+
+// A device-input call issued while the caller captures `st` into a graph of
+// its own.  The launches go straight into that capture: no graph of the
+// library's, no event waits or records, no timing.  The call gets a work set
+// of its own, allocated now and kept until the context ends, so that replays
+// of the caller's graph neither race with other calls into the library nor
+// lose their buffers when the shared set grows.  Its accumulator words are
+// cleared by a kernel at the start of every replay.
+int32_t Context::run_captured(const Launch &L, hipStream_t st)
+{
+    const int64_t rows = (int64_t)L.count * PERM_MAX_N;
+    std::unique_ptr<DevBuf> buf(new DevBuf());
+    // allocation is not a stream operation; let it pass a capture in global mode
+    hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+    HIP_TRY(hipThreadExchangeStreamCaptureMode(&mode));
+    const hipError_t e = buf->reserve(workset_bytes(L.count, rows, true));
+    (void)hipThreadExchangeStreamCaptureMode(&mode);
+    if (e != hipSuccess) return hip_fail(e, "work buffers for a captured call");
+    const WorkSet w = workset_carve(buf->p, L.count, rows, true);
+    captured.push_back(std::move(buf));
+    Launch C = L;
+    C.zero_acc = L.count <= SMALL_PLAN_MAX ? 1 : 0;
+    const int32_t rc = enqueue(C, w, tuning, st, false);
+    last_timing_valid = false;
+    last_graph = 0;
+    return rc;
 }
 
 // A device-input call on the caller's stream.  For a NULL stream (where torch
@@ -415,9 +489,11 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
                           uint64_t lo, uint64_t hi, uint8_t *out_host, int64_t *tally_host)
 {
     int64_t bytes = 0, rows = 0;
+    int32_t nmax = 0;
     for (int32_t k = 0; k < count; ++k) {
         bytes += (int64_t)ns[k] * ns[k];
         rows += ns[k];
+        nmax = std::max(nmax, ns[k]);
     }
     const size_t offs_bytes = (size_t)count * sizeof(int64_t);
     const size_t ns_bytes = (size_t)count * sizeof(int32_t);
@@ -426,15 +502,9 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     const size_t stage_bytes = ns_at + ns_bytes;
     // the orders are known here: a small call whose walk k_small takes alone
     // needs no k_walk after it (the kernel makes the same decision)
-    uint64_t work = 0;
-    int32_t nmax = 0;
-    for (int32_t k = 0; k < count; ++k) {
-        work += 1ull << ns[k];
-        nmax = std::max(nmax, ns[k]);
-    }
-    const bool fused_only = count <= SMALL_PLAN_MAX && !use_range && work <= SMALL_FUSED_WORK;
+    const bool fused_only = small_call_fused(ns, count, use_range);
     uint64_t tasks = 0;
-    if (fused_only) tasks = small_call_tasks(plan_args(nullptr, count, nullptr, nullptr), ns, count);
+    if (fused_only) tasks = small_call_tasks(plan_args(ws, tuning, nullptr, count, nullptr, nullptr), ns, count);
     // Such a call reads its inputs straight from coherent pinned memory when
     // that moves little over the host link (each of its waves reads the
     // orders, the offsets and its matrix once): no staging copy before it.
@@ -487,7 +557,7 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     if (fused_only) L.small_blocks = (int32_t)std::min<uint64_t>((tasks + 3) / 4, (uint64_t)grid_blocks());
     rc = run(L, st, false);
     if (rc) return rc;
-    if (tally_host) HIP_TRY(hipMemcpyAsync(tally_host, tally.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if (tally_host) HIP_TRY(hipMemcpyAsync(tally_host, ws.tally, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (out_host) memcpy(out_host, h_out.p, (size_t)count);
     return PERM_OK;
@@ -593,6 +663,34 @@ int32_t perm_mod3_batch(const uint8_t *const *As, const int32_t *ns, int32_t cou
     return c->run_host(As, ns, count, false, 0, 0, out, nullptr);
 }
 
+// The device-input calls: into the caller's capture when `stream` is being
+// captured, else eagerly or through the library's cached graphs.
+static int32_t run_device_call(Launch &L, void *stream)
+{
+    const hipStream_t st = (hipStream_t)stream;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (st) HIP_TRY(hipStreamIsCapturing(st, &cs));
+    if (cs == hipStreamCaptureStatusInvalidated)
+        return set_error(PERM_EDEVICE, "the stream's capture has been invalidated");
+    const bool capturing = cs == hipStreamCaptureStatusActive;
+    Context *c = nullptr;
+    int32_t rc;
+    if (capturing) {
+        // making the context (first call on a device) is no stream operation either
+        hipStreamCaptureMode mode = hipStreamCaptureModeRelaxed;
+        HIP_TRY(hipThreadExchangeStreamCaptureMode(&mode));
+        rc = get_context(&c);
+        (void)hipThreadExchangeStreamCaptureMode(&mode);
+    } else {
+        rc = get_context(&c);
+    }
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    if (capturing) return c->run_captured(L, st);
+    if ((rc = c->reserve_work(L.count, (int64_t)L.count * PERM_MAX_N))) return rc;
+    return c->run_dev(L, st);
+}
+
 int32_t perm_mod3_batch_dev(const uint8_t *mats_dev, const int64_t *offs_dev, const int32_t *ns_dev,
                             int32_t count, uint8_t *out_dev, uint64_t *hist_dev, void *stream)
 {
@@ -600,11 +698,6 @@ int32_t perm_mod3_batch_dev(const uint8_t *mats_dev, const int64_t *offs_dev, co
     if (count < 0 || count > PERM_MAX_BATCH) return set_error(PERM_EINVAL, "count = %d out of range", count);
     if (count == 0) return PERM_OK;
     if (!mats_dev || !offs_dev || !ns_dev || !out_dev) return set_error(PERM_EINVAL, "null pointer argument");
-    Context *c = nullptr;
-    int32_t rc = get_context(&c);
-    if (rc) return rc;
-    std::lock_guard<std::mutex> g(c->mu);
-    if ((rc = c->reserve_work(count, (int64_t)count * PERM_MAX_N))) return rc;
     Launch L;
     memset(&L, 0, sizeof L);
     L.pack_kind = 0;
@@ -614,7 +707,7 @@ int32_t perm_mod3_batch_dev(const uint8_t *mats_dev, const int64_t *offs_dev, co
     L.count = count;
     L.out_dev = out_dev;
     L.hist_dev = hist_dev;
-    return c->run_dev(L, (hipStream_t)stream);
+    return run_device_call(L, stream);
 }
 
 int32_t perm_mod3_batch_packed(const uint64_t *planes_dev, const int64_t *row_off_dev, const int32_t *ns_dev,
@@ -625,11 +718,6 @@ int32_t perm_mod3_batch_packed(const uint64_t *planes_dev, const int64_t *row_of
     if (count == 0) return PERM_OK;
     if (!planes_dev || !row_off_dev || !ns_dev || !out_dev)
         return set_error(PERM_EINVAL, "null pointer argument");
-    Context *c = nullptr;
-    int32_t rc = get_context(&c);
-    if (rc) return rc;
-    std::lock_guard<std::mutex> g(c->mu);
-    if ((rc = c->reserve_work(count, (int64_t)count * PERM_MAX_N))) return rc;
     Launch L;
     memset(&L, 0, sizeof L);
     L.pack_kind = 1;
@@ -639,7 +727,37 @@ int32_t perm_mod3_batch_packed(const uint64_t *planes_dev, const int64_t *row_of
     L.count = count;
     L.out_dev = out_dev;
     L.hist_dev = hist_dev;
-    return c->run_dev(L, (hipStream_t)stream);
+    return run_device_call(L, stream);
+}
+
+int32_t perm_mod3_from_tallies(int32_t n, const int64_t *tallies, int32_t count, uint8_t *out)
+{
+    set_error_index(-1);
+    if (n < 0 || n > PERM_MAX_N) return set_error(PERM_EINVAL, "n = %d is outside [0, %d]", n, PERM_MAX_N);
+    if (count < 1 || count > PERM_MAX_TALLIES)
+        return set_error(PERM_EINVAL, "count = %d is outside [1, %d]", count, PERM_MAX_TALLIES);
+    if (!tallies || !out) return set_error(PERM_EINVAL, "null pointer argument");
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    const size_t bytes = (size_t)count * sizeof(int64_t);
+    HIP_TRY(c->h_zc.reserve(bytes));
+    HIP_TRY(c->h_out.reserve(1));
+    memcpy(c->h_zc.p, tallies, bytes);
+    int64_t *t_dev = nullptr;
+    uint8_t *out_dev = nullptr;
+    HIP_TRY(hipHostGetDevicePointer((void **)&t_dev, c->h_zc.p, 0));
+    HIP_TRY(hipHostGetDevicePointer((void **)&out_dev, c->h_out.p, 0));
+    const hipStream_t st = c->stream;
+    if ((rc = c->join(st))) return rc;
+    HIP_TRY(launch_finish_tallies(t_dev, count, n, out_dev, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    *out = *(volatile uint8_t *)c->h_out.p;
+    c->last_timing_valid = false;
+    c->last_launches = 1;
+    c->last_graph = 0;
+    return c->mark(st);
 }
 
 int32_t perm_mod3_pack(const uint8_t *A, int32_t n, uint64_t *planes)
@@ -736,7 +854,7 @@ int32_t perm_mod3_census(int32_t n, int32_t generator, uint64_t key, uint64_t fi
             L.count = (int32_t)cnt;
             L.out_dev = out;
             L.hist_dev = (uint64_t *)dcounts;
-            if ((rc = c->enqueue(L, st, false))) return rc;
+            if ((rc = c->enqueue(L, c->ws, c->tuning, st, false))) return rc;
         }
     }
     uint64_t h[64 * 3];

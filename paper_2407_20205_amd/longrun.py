@@ -4,10 +4,12 @@ The range [0, 2^n) is cut into equal shards; each shard's exact partial
 tally T(a, b) is computed by ``tally_fn`` (by default the library's
 ``perm_mod3_range_tally``) and recorded in a JSON checkpoint together with
 the matrix hash, so an interrupted run resumes where it stopped and a
-checkpoint of another matrix is refused.  Because tallies are additive,
-perm(A) mod 3 = (-1)^n * sum of the shard tallies mod 3 (Section 3.1's
-blocks of consecutive Gray states); a shard is also exactly what one GPU of
-several would take.
+checkpoint of another matrix is refused.  This module only does that
+bookkeeping: the shard tallies are summed and reduced, (-1)^n times their
+sum mod 3 (Section 3.1's blocks of consecutive Gray states, eq. (2)), by
+``finish_fn``, by default the library's ``perm_mod3_from_tallies``, which
+does it on the device.  A shard is also exactly what one GPU of several
+would take.
 """
 from __future__ import annotations
 
@@ -39,9 +41,9 @@ def _save(path: str, state: dict) -> None:
     os.replace(tmp, path)
 
 
-def sharded_tally(A, shards: int, tally_fn: Callable | None = None, checkpoint: str | None = None,
-                  log: Callable | None = None) -> int:
-    """Sum of the shard tallies of A; resumes from ``checkpoint`` if it exists."""
+def sharded_tallies(A, shards: int, tally_fn: Callable | None = None, checkpoint: str | None = None,
+                    log: Callable | None = None) -> list[int]:
+    """The tally of every shard of A, in shard order; resumes from ``checkpoint`` if it exists."""
     A = np.ascontiguousarray(A, dtype=np.uint8)
     n = A.shape[0]
     if shards < 1 or shards > (1 << n):
@@ -68,12 +70,15 @@ def sharded_tally(A, shards: int, tally_fn: Callable | None = None, checkpoint: 
         if log:
             log(f"shard {k + 1}/{shards} [{a}, {b}) tally {state['done'][str(k)]} "
                 f"in {time.perf_counter() - t0:.2f} s")
-    return sum(int(v) for v in state["done"].values())
+    return [int(state["done"][str(k)]) for k in range(shards)]
 
 
-def perm_mod3_sharded(A, shards: int, **kw) -> int:
-    """perm(A) mod 3 in {0, 1, 2} from a sharded, checkpointed run."""
+def perm_mod3_sharded(A, shards: int, finish_fn: Callable | None = None, **kw) -> int:
+    """perm(A) mod 3 in {0, 1, 2} from a sharded, checkpointed run; ``finish_fn(n, tallies)``
+    reduces the shard tallies (default: the library's perm_mod3_from_tallies)."""
     A = np.ascontiguousarray(A, dtype=np.uint8)
-    T = sharded_tally(A, shards, **kw)
-    p = -T if A.shape[0] % 2 else T
-    return p % 3
+    tallies = sharded_tallies(A, shards, **kw)
+    if finish_fn is None:
+        from . import perm3
+        finish_fn = perm3.perm_mod3_from_tallies
+    return int(finish_fn(A.shape[0], tallies))

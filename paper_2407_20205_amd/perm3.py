@@ -36,6 +36,7 @@ PERM_F3_MUL = 2
 PERM_F3_DIV = 3
 PERM_F3_NEG = 4
 PERM_F3_MAX_LEN = 1 << 40
+PERM_MAX_TALLIES = 1 << 20
 PERM_POLICY_SRPT = 0
 PERM_POLICY_FIFO = 1
 
@@ -106,6 +107,7 @@ EXPORTS = [
     ("perm_mod3_batch", _i32, [_vp, _vp, _i32, _vp]),
     ("perm_mod3_batch_dev", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     ("perm_mod3_batch_packed", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    ("perm_mod3_from_tallies", _i32, [_i32, _vp, _i32, _vp]),
     ("perm_mod3_pack", _i32, [_vp, _i32, _vp]),
     ("perm_mod3_census", _i32, [_i32, _i32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _vp]),
     ("perm_server_create", _i32, [_vp, _vp]),
@@ -213,7 +215,68 @@ def perm_mod3_census(n: int, generator: int, key: int, first: int, count: int) -
     return int(c[0]), int(c[1]), int(c[2])
 
 
+def perm_mod3_from_tallies(n: int, tallies) -> int:
+    """perm(A) mod 3 of an n x n matrix from the exact tallies of Gray ranges covering [0, 2^n) once
+    (the shards of a long run); the sum and its reduction run on the device."""
+    t = np.ascontiguousarray(np.asarray(tallies, dtype=np.int64).reshape(-1))
+    out = ctypes.c_uint8(0)
+    _check(lib().perm_mod3_from_tallies(n, _ptr(t) if t.size else None, int(t.size), ctypes.addressof(out)))
+    return int(out.value)
+
+
 # ---------------------------------------------------------------- device calls (torch tensors)
+#
+# The C calls take raw device addresses and sizes; a tensor of the wrong type,
+# length or device would send the kernels outside their buffers.  Each tensor
+# is therefore checked here, before any C call: dtype, contiguity, length and
+# device, in that order.
+
+def _dtypes(*names):
+    import torch
+    return tuple(getattr(torch, k) for k in names if hasattr(torch, k))
+
+
+def _need(t, name, dtypes, min_numel):
+    """Check one tensor argument's type, layout and length."""
+    if t is None:
+        raise ValueError(f"{name} is required")
+    if not hasattr(t, "data_ptr") or not hasattr(t, "dtype"):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype not in dtypes:
+        raise ValueError(f"{name} must have dtype {' or '.join(str(d) for d in dtypes)}, not {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() < min_numel:
+        raise ValueError(f"{name} holds {t.numel()} elements; the call needs at least {min_numel}")
+
+
+def _one_device(**tensors):
+    """Every given tensor (None skipped) on the same CUDA device."""
+    dev = None
+    for name, t in tensors.items():
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError(f"{name} must be on a CUDA device, not {t.device}")
+        if dev is None:
+            dev = t.device
+        elif t.device != dev:
+            raise ValueError(f"{name} is on {t.device}, the other tensors on {dev}")
+
+
+def _check_batch_args(first, first_name, first_dtypes, index, index_name, ns_dev, out_dev, hist_dev):
+    """Arguments of the batched device calls; returns count."""
+    i32, i64, u8 = _dtypes("int32"), _dtypes("int64"), _dtypes("uint8")
+    _need(ns_dev, "ns_dev", i32, 0)
+    count = int(ns_dev.numel())
+    _need(first, first_name, first_dtypes, 0)
+    _need(index, index_name, i64, count)
+    _need(out_dev, "out_dev", u8, count)
+    if hist_dev is not None:
+        _need(hist_dev, "hist_dev", _dtypes("int64", "uint64"), 64 * 3)
+    _one_device(ns_dev=ns_dev, **{first_name: first, index_name: index}, out_dev=out_dev, hist_dev=hist_dev)
+    return count
+
 
 def _dptr(t) -> int | None:
     return None if t is None else int(t.data_ptr())
@@ -226,14 +289,17 @@ def _stream(stream) -> int | None:
 
 
 def perm_mod3_batch_dev(mats_dev, offs_dev, ns_dev, out_dev, hist_dev=None, stream=None) -> None:
-    """All tensors on the GPU: uint8 bytes, int64 offsets, int32 n, uint8 out, uint64/int64 hist[64*3]."""
-    count = int(ns_dev.numel())
+    """All tensors on one GPU: uint8 bytes, int64 offsets, int32 n, uint8 out, int64/uint64 hist[64*3]."""
+    count = _check_batch_args(mats_dev, "mats_dev", _dtypes("uint8"), offs_dev, "offs_dev", ns_dev, out_dev,
+                              hist_dev)
     _check(lib().perm_mod3_batch_dev(_dptr(mats_dev), _dptr(offs_dev), _dptr(ns_dev), count,
                                      _dptr(out_dev), _dptr(hist_dev), _stream(stream)))
 
 
 def perm_mod3_batch_packed(planes_dev, row_off_dev, ns_dev, out_dev, hist_dev=None, stream=None) -> None:
-    count = int(ns_dev.numel())
+    """planes_dev: int64/uint64 (mag, sgn) word pairs; row_off_dev: int64 first row per matrix."""
+    count = _check_batch_args(planes_dev, "planes_dev", _dtypes("int64", "uint64"), row_off_dev, "row_off_dev",
+                              ns_dev, out_dev, hist_dev)
     _check(lib().perm_mod3_batch_packed(_dptr(planes_dev), _dptr(row_off_dev), _dptr(ns_dev), count,
                                         _dptr(out_dev), _dptr(hist_dev), _stream(stream)))
 
@@ -245,27 +311,53 @@ def f3_words(length: int) -> int:
     return (length + 63) // 64
 
 
+def _planes_dtypes():
+    return _dtypes("int64", "uint64")
+
+
 def f3_pack(v_dev, planes_dev, invalid_dev=None, stream=None) -> None:
     """phi: uint8 tensor v_dev (values 0, 1, 2) into int64 planes_dev[2 * f3_words(len)]; bytes > 2 are
     packed as 0 and their count is added to invalid_dev[0] (int64/uint64 tensor) when given."""
-    _check(lib().perm_f3_pack(_dptr(v_dev), int(v_dev.numel()), _dptr(planes_dev), _dptr(invalid_dev),
-                              _stream(stream)))
+    _need(v_dev, "v_dev", _dtypes("uint8"), 0)
+    length = int(v_dev.numel())
+    _need(planes_dev, "planes_dev", _planes_dtypes(), 2 * f3_words(length))
+    if invalid_dev is not None:
+        _need(invalid_dev, "invalid_dev", _planes_dtypes(), 1)
+    _one_device(v_dev=v_dev, planes_dev=planes_dev, invalid_dev=invalid_dev)
+    _check(lib().perm_f3_pack(_dptr(v_dev), length, _dptr(planes_dev), _dptr(invalid_dev), _stream(stream)))
 
 
 def f3_unpack(planes_dev, length: int, v_dev, stream=None) -> None:
     """psi: planes into uint8 v_dev[length]."""
+    # a negative length is refused by the C call (PERM_EINVAL)
+    _need(planes_dev, "planes_dev", _planes_dtypes(), 2 * f3_words(max(length, 0)))
+    _need(v_dev, "v_dev", _dtypes("uint8"), max(length, 0))
+    _one_device(planes_dev=planes_dev, v_dev=v_dev)
     _check(lib().perm_f3_unpack(_dptr(planes_dev), length, _dptr(v_dev), _stream(stream)))
 
 
 def f3_op(op: int, a_dev, b_dev, out_dev, words: int | None = None, stream=None) -> None:
     """out = a op b (Theorem 2.1) over `words` word pairs (default: all of a)."""
+    _need(a_dev, "a_dev", _planes_dtypes(), 0)
     w = int(a_dev.numel()) // 2 if words is None else words
+    need = 2 * max(w, 0)          # a negative count is refused by the C call (PERM_EINVAL)
+    _need(a_dev, "a_dev", _planes_dtypes(), need)
+    if op != PERM_F3_NEG or b_dev is not None:
+        _need(b_dev, "b_dev", _planes_dtypes(), need)
+    _need(out_dev, "out_dev", _planes_dtypes(), need)
+    _one_device(a_dev=a_dev, b_dev=b_dev, out_dev=out_dev)
     _check(lib().perm_f3_op(op, _dptr(a_dev), _dptr(b_dev), _dptr(out_dev), w, _stream(stream)))
 
 
 def f3_dot(a_dev, b_dev, sum_dev, words: int | None = None, stream=None) -> None:
     """sum_dev[0] (int64 tensor) = sum_e a_e b_e over the integers; the F_3 dot product is it mod 3."""
+    _need(a_dev, "a_dev", _planes_dtypes(), 0)
     w = int(a_dev.numel()) // 2 if words is None else words
+    need = 2 * max(w, 0)
+    _need(a_dev, "a_dev", _planes_dtypes(), need)
+    _need(b_dev, "b_dev", _planes_dtypes(), need)
+    _need(sum_dev, "sum_dev", _dtypes("int64"), 1)
+    _one_device(a_dev=a_dev, b_dev=b_dev, sum_dev=sum_dev)
     _check(lib().perm_f3_dot(_dptr(a_dev), _dptr(b_dev), w, _dptr(sum_dev), _stream(stream)))
 
 

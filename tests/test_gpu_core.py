@@ -264,3 +264,20 @@ def test_autotune_keeps_results():
         assert P.perm_mod3(A) == oracle.perm_mod3(A)
     finally:
         P.tuning_set(saved)
+
+
+def test_from_tallies_finishes_shards():
+    from paper_2407_20205_amd import longrun
+    A = W.uniform_matrix(28, 91)
+    shards = [P.perm_mod3_range_tally(A, *longrun.shard_bounds(28, 7, k)) for k in range(7)]
+    assert P.perm_mod3_from_tallies(28, shards) == oracle.perm_mod3(A)
+    # (-1)^n times the sum, mod 3, for arbitrary tallies and both parities of n
+    g = W.rng(92)
+    for n in (0, 1, 2, 33, 62, 63):
+        for size in (1, 63, 64, 65, 1000):
+            ts = g.integers(-(1 << 40), 1 << 40, size=size)
+            assert P.perm_mod3_from_tallies(n, ts) == oracle.perm_from_tally(n, int(ts.sum())), (n, size)
+    for bad in [(64, [1]), (-1, [1]), (5, [])]:
+        with pytest.raises(P.PermError) as e:
+            P.perm_mod3_from_tallies(*bad)
+        assert e.value.code == P.PERM_EINVAL

@@ -44,12 +44,19 @@ def test_pi_matrix_readings():
     assert [int(x) for x in B[7]] == [int(c) % 3 for c in d[343:393]]
 
 
-def test_sharded_tally_matches_whole_range(tmp_path):
+def oracle_finish(n, tallies):
+    return oracle.perm_from_tally(n, sum(tallies))
+
+
+def test_sharded_tallies_match_whole_range(tmp_path):
     A = W.uniform_matrix(14, 8)
     whole = oracle.range_tally(A, 0, 1 << 14)
     for shards in (1, 3, 16, 100):
-        assert longrun.sharded_tally(A, shards, tally_fn=oracle.range_tally) == whole
-    assert longrun.perm_mod3_sharded(A, 7, tally_fn=oracle.range_tally) == oracle.perm_mod3(A)
+        ts = longrun.sharded_tallies(A, shards, tally_fn=oracle.range_tally)
+        assert len(ts) == shards and sum(ts) == whole
+        assert ts == [oracle.range_tally(A, *longrun.shard_bounds(14, shards, k)) for k in range(shards)]
+    got = longrun.perm_mod3_sharded(A, 7, tally_fn=oracle.range_tally, finish_fn=oracle_finish)
+    assert got == oracle.perm_mod3(A)
 
 
 def test_checkpoint_resume_after_interruption(tmp_path):
@@ -67,19 +74,19 @@ def test_checkpoint_resume_after_interruption(tmp_path):
         return oracle.range_tally(M, a, b)
 
     with pytest.raises(Interrupted):
-        longrun.sharded_tally(A, 12, tally_fn=flaky, checkpoint=ck)
+        longrun.sharded_tallies(A, 12, tally_fn=flaky, checkpoint=ck)
     state = json.load(open(ck))
     assert len(state["done"]) == 4                # four shards were saved before the failure
     calls.clear()
-    total = longrun.sharded_tally(A, 12, tally_fn=lambda M, a, b: (calls.append((a, b)), oracle.range_tally(M, a, b))[1],
-                                  checkpoint=ck)
+    ts = longrun.sharded_tallies(A, 12, tally_fn=lambda M, a, b: (calls.append((a, b)), oracle.range_tally(M, a, b))[1],
+                                 checkpoint=ck)
     assert len(calls) == 8                         # only the missing shards ran again
-    assert total == oracle.range_tally(A, 0, 1 << 13)
+    assert sum(ts) == oracle.range_tally(A, 0, 1 << 13)
     # a checkpoint of another matrix or sharding is refused
     with pytest.raises(ValueError):
-        longrun.sharded_tally(W.uniform_matrix(13, 10), 12, tally_fn=oracle.range_tally, checkpoint=ck)
+        longrun.sharded_tallies(W.uniform_matrix(13, 10), 12, tally_fn=oracle.range_tally, checkpoint=ck)
     with pytest.raises(ValueError):
-        longrun.sharded_tally(A, 11, tally_fn=oracle.range_tally, checkpoint=ck)
+        longrun.sharded_tallies(A, 11, tally_fn=oracle.range_tally, checkpoint=ck)
 
 
 def test_shard_bounds_cover_the_range():
