@@ -70,6 +70,12 @@ def measured_traffic():
     return d["traffic_bytes_per_launch"] if d else None
 
 
+def tuning_info(P, cls):
+    """Which tuning a class of call runs with: its source (default, cache, set, autotune) and values."""
+    t, src = P.tuning_get_class(cls)
+    return {"class": P.TUNE_CLASS_NAMES[cls], "source": P.TUNE_SOURCE_NAMES[src], "values": t.as_dict()}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -131,6 +137,11 @@ def bench_headline(P, W, torch, steps, warmup):
         "paper_ops_frac": PAPER_OPS_PER_TERM_2W * terms / hot_s / PEAK_LANE_OPS,
     }
     d = walk_counters()
+    # traffic, executed_frac and valu_utilization_pct are not measured in this run: they come from
+    # the committed counter passes, used only while the kernel sources hash to the profiled ones
+    res["roofline"]["counters_source"] = (
+        {"file": "profiles/k_walk_36x36_counters.json", "source_sha256": d["source_sha256"],
+         "fields": ["traffic", "executed_frac", "valu_utilization_pct"]} if d else None)
     if d:
         # executed VALU lane-ops (SQ_INSTS_VALU x 64 per index, from the counter pass) over the peak,
         # and rocprof's VALUUtilization
@@ -138,6 +149,15 @@ def bench_headline(P, W, torch, steps, warmup):
         if "valu_utilization_pct" in d:
             res["roofline"]["valu_utilization_pct"] = d["valu_utilization_pct"]
     return res
+
+
+def with_default_tuning(P, cls, fn):
+    """Run fn() with every class at the library's defaults (None when class cls already runs them)."""
+    if P.tuning_get_class(cls)[1] == P.PERM_TUNE_SRC_DEFAULT:
+        return None
+    with P.saved_tunings():
+        P.tuning_reset()
+        return fn()
 
 
 # ------------------------------------------------------------------ batch
@@ -478,11 +498,11 @@ def expected_work(W):
     return float(sum(pi * (2.0 ** int(n)) for n, pi in zip(support, p)))
 
 
-def replay_server(P, tr, policy, quantum):
+def replay_server(P, tr, policy, quantum, work_budget=1 << 44):
     """Open-loop replay: requests are submitted at their arrival times; latency = done - arrival."""
     count = len(tr.mats)
     done = {}
-    srv = P.Server(max_slots=4096, queue_cap=1 << 16, work_budget=1 << 44, quantum=quantum, policy=policy)
+    srv = P.Server(max_slots=4096, queue_cap=1 << 16, work_budget=work_budget, quantum=quantum, policy=policy)
     start = time.monotonic_ns()
     stop = threading.Event()
 
@@ -542,6 +562,11 @@ def bench_serve(P, W, torch, rate, count, batched_terms_per_s, quantum=1 << 33, 
     if not baseline:
         return {"rate_per_s": rate, "quantum": quantum, "requests_per_s": count / span, "p50_ms": pct(lat, 50),
                 "p99_ms": pct(lat, 99), "ticks": int(st.ticks)}
+    # the same trace with a work budget that binds: at most 2^36 Gray indices admitted at once
+    # (one 36 x 36 request's work), so larger requests run alone and later ones wait in the queue
+    budget = 1 << 36
+    qlat, qres, qspan, qst = replay_server(P, tr, P.PERM_POLICY_SRPT, quantum, work_budget=budget)
+    log(f"serve: budget 2^36 done in {qspan:.2f} s, p50 {pct(qlat, 50):.3f} ms, p99 {pct(qlat, 99):.3f} ms")
     blat, bres, bspan = replay_fifo_baseline(P, tr)
     log(f"serve: FIFO baseline done in {bspan:.2f} s")
     return {
@@ -557,6 +582,10 @@ def bench_serve(P, W, torch, rate, count, batched_terms_per_s, quantum=1 << 33, 
         "baseline_fifo_one_launch_per_request": {"p50_ms": pct(blat, 50), "p99_ms": pct(blat, 99),
                                                  "requests_per_s": count / bspan},
         "results_identical_to_baseline": bool(res == bres),
+        "work_budget": 1 << 44,
+        "budgeted_2pow36": {"work_budget": budget, "requests_per_s": count / qspan, "p50_ms": pct(qlat, 50),
+                            "p99_ms": pct(qlat, 99), "mean_ms": float(np.mean(qlat)), "ticks": int(qst.ticks),
+                            "results_identical": bool(qres == res)},
     }
 
 
@@ -648,13 +677,24 @@ def main():
         log(f"copy probe: {nbytes} bytes device to device")
         del src, dst
     if args.only in (None, "headline"):
+        tune = tuning_info(P, P.PERM_TUNE_LARGE)
         h = bench_headline(P, W, torch, args.steps, args.warmup)
         log(f"headline: {h['terms_per_s']:.4e} terms/s, walk {h['hot_kernel_ms_mean']:.3f} ms, "
-            f"frac {h['roofline']['frac']:.3f}")
+            f"frac {h['roofline']['frac']:.3f} (tuning: {tune['source']})")
         line["value"] = h["terms_per_s"]
         line["ms_per_step"] = h["ms_per_step"]
         line["roofline"] = h["roofline"]
+        line["roofline"]["tuning_source"] = tune["source"]
         line["headline_detail"] = {k: v for k, v in h.items() if k != "roofline"}
+        line["headline_detail"]["tuning"] = tune
+        hd = with_default_tuning(P, P.PERM_TUNE_LARGE,
+                                 lambda: bench_headline(P, W, torch, max(5, args.steps // 2), args.warmup))
+        if hd is not None:
+            line["headline_default_tuning"] = {
+                "terms_per_s": hd["terms_per_s"], "hot_kernel_ms_mean": hd["hot_kernel_ms_mean"],
+                "frac": hd["roofline"]["frac"], "result": hd["result"], "steps": max(5, args.steps // 2)}
+            log(f"headline with default tuning: {hd['terms_per_s']:.4e} terms/s, "
+                f"walk {hd['hot_kernel_ms_mean']:.3f} ms")
         line["vs_paper_one_core"] = h["terms_per_s"] / ((1 << 36) / 101.9)
     if args.only in (None, "single20"):
         s20 = bench_single20(P, W, torch)
@@ -662,8 +702,18 @@ def main():
             f"(host call: p50 {s20['host_call']['p50_us']:.1f} us, p99 {s20['host_call']['p99_us']:.1f} us)")
         line["single20"] = s20
     if args.only in (None, "batch"):
+        tune = tuning_info(P, P.PERM_TUNE_BATCH)
         bt = bench_batch(P, W, torch, reps=max(3, args.steps // 4), baseline=not args.no_baselines)
-        log(f"batch: {bt['matrices_per_s']:.1f} matrices/s ({bt.get('speedup_vs_baseline', 0):.1f}x one-launch)")
+        bt["tuning"] = tune
+        log(f"batch: {bt['matrices_per_s']:.1f} matrices/s ({bt.get('speedup_vs_baseline', 0):.1f}x one-launch, "
+            f"tuning: {tune['source']})")
+        bd = with_default_tuning(P, P.PERM_TUNE_BATCH,
+                                 lambda: bench_batch(P, W, torch, reps=max(3, args.steps // 4), baseline=False))
+        if bd is not None:
+            bt["default_tuning"] = {"matrices_per_s": bd["matrices_per_s"], "terms_per_s": bd["terms_per_s"],
+                                    "ms_per_batch": bd["ms_per_batch"],
+                                    "hist_identical": bd["hist_per_n"] == bt["hist_per_n"]}
+            log(f"batch with default tuning: {bd['matrices_per_s']:.1f} matrices/s")
         line["batch"] = bt
     if args.only in (None, "serve"):
         cap = line.get("batch", {}).get("terms_per_s") or 8e12

@@ -328,11 +328,86 @@ typedef struct {
     int32_t reserved[1];
 } perm_tuning;
 
+/*
+ * The context keeps one tuning per class of call.  The block decomposition of
+ * Section 3.1 (how long a lane's run of consecutive Gray states is, how many
+ * runs make a task, how many waves take tasks) is a free choice that does not
+ * change any result; what runs fastest differs between one large matrix, one
+ * small one and a batch of mixed orders.  A call's class:
+ *   PERM_TUNE_SMALL  host calls of one matrix with n <= 24 (latency bound)
+ *   PERM_TUNE_MID    host calls of one matrix with 25 <= n <= 31
+ *   PERM_TUNE_LARGE  host calls of one matrix with n >= 32; one-matrix
+ *                    device-input calls (the host does not read their order);
+ *                    the 128-column walk
+ *   PERM_TUNE_BATCH  calls of two or more matrices, the census, the server
+ * The host calls perm_mod3 and perm_mod3_range_tally count as calls of one
+ * matrix.
+ */
+#define PERM_TUNE_SMALL   0
+#define PERM_TUNE_MID     1
+#define PERM_TUNE_LARGE   2
+#define PERM_TUNE_BATCH   3
+#define PERM_TUNE_CLASSES 4
+
+/* where a class's tuning came from */
+#define PERM_TUNE_SRC_DEFAULT  0   /* the library's built-in defaults              */
+#define PERM_TUNE_SRC_CACHE    1   /* a tuning cache file (perm_tuning_cache_load) */
+#define PERM_TUNE_SRC_SET      2   /* perm_tuning_set / perm_tuning_set_class      */
+#define PERM_TUNE_SRC_AUTOTUNE 3   /* perm_autotune / perm_autotune_batch          */
+
+/* perm_tuning_get: the tuning of class PERM_TUNE_LARGE.  perm_tuning_set:
+ * one tuning for every class.  Both act on the current device's context. */
 int32_t perm_tuning_get(perm_tuning *t);
 int32_t perm_tuning_set(const perm_tuning *t);
-/* Time candidate tunings on the device on synthetic matrices of size n and
- * keep the fastest; budget_ms bounds the search.  Writes the winner to *best. */
+/* One class's tuning and its source (source may be NULL). */
+int32_t perm_tuning_get_class(int32_t cls, perm_tuning *t, int32_t *source);
+int32_t perm_tuning_set_class(int32_t cls, const perm_tuning *t);
+/* Every class back to the built-in defaults (source PERM_TUNE_SRC_DEFAULT). */
+int32_t perm_tuning_reset(void);
+
+/*
+ * Tuning cache: a text file, one line per (device, class):
+ *     <arch> <compute units> <class name> key=value ...
+ * with the class names small, mid, large, batch and the keys the fields of
+ * perm_tuning; '#' starts a comment.  perm_tuning_cache_load applies the lines
+ * whose arch (the gcnArchName, e.g. "gfx950:sramecc+:xnack-") and compute
+ * unit count equal the current device's; lines for other devices, unknown
+ * keys and out-of-range tunings are skipped.  *loaded (may be NULL) = classes
+ * set.  PERM_EINVAL if the file cannot be opened.
+ * perm_tuning_cache_save writes the current device's classes whose source is
+ * not the default, keeping every other line of an existing file; the file is
+ * replaced atomically.
+ * When a context is made, the library loads the file named by the environment
+ * variable PERM3_TUNING_CACHE (none when it is set but empty), else the file
+ * perm3_tuning.txt beside libperm3.so, if there is one.
+ */
+int32_t perm_tuning_cache_load(const char *path, int32_t *loaded);
+int32_t perm_tuning_cache_save(const char *path);
+
+/*
+ * perm_autotune: time candidate tunings of the class a one-matrix host call
+ * of order n falls in (12 <= n <= 63) on a synthetic uniform n x n matrix and
+ * keep the fastest as that class's tuning (source PERM_TUNE_SRC_AUTOTUNE).
+ * The search covers the persistent waves per SIMD, the per-lane chunk length
+ * (chunk_log_max, tasks_per_wave, and the per-matrix task bounds), the block
+ * length and the chunks per lane, by successive halving: every candidate is
+ * timed once, the faster half again with twice the repetitions, and so on;
+ * the class's current tuning is always a candidate.  budget_ms bounds the
+ * search (the first round always completes).  Classes SMALL and MID are timed
+ * by the whole call's wall time, LARGE by the walk kernel's HIP events over
+ * 2^min(n, 36) Gray indices.  Writes the winner to *best.
+ */
 int32_t perm_autotune(int32_t n, int32_t budget_ms, perm_tuning *best);
+
+/*
+ * perm_autotune_batch: the same search for class PERM_TUNE_BATCH, timed on the
+ * caller's own batch (arguments as perm_mod3_batch_packed; out_dev receives
+ * the results of the last timed run).  Each candidate's time is the whole
+ * call's (plan, pack, walk) by HIP events on the library's stream.
+ * Synchronous.
+ */
+int32_t perm_autotune_batch(const uint64_t *planes_dev, const int64_t *row_off_dev, const int32_t *ns_dev,
+                            int32_t count, uint8_t *out_dev, int32_t budget_ms, perm_tuning *best);
 
 typedef struct {
     double   hot_kernel_ms;   /* Gray-walk kernel of the last call, HIP events on its stream */

@@ -20,6 +20,8 @@ void set_error_index(int64_t idx);
 int32_t hip_fail(hipError_t e, const char *what);
 perm_tuning default_tuning();
 bool tuning_valid(const perm_tuning &t);
+// The tuning class of a host call of `count` matrices whose first order is n0.
+int tune_class_host(int32_t count, int32_t n0);
 
 struct DevBuf {
     void *p = nullptr;
@@ -80,6 +82,7 @@ struct Launch {
     int32_t fused_only;           // the caller knows the call is walked by k_small alone
     int32_t small_blocks;         // k_small's grid when the caller knows the work (0: the full grid)
     int32_t zero_acc;             // clear the accumulator words first (a set not known to hold zeros)
+    int32_t cls;                  // tuning class (PERM_TUNE_*)
 };
 
 using GraphKey = std::tuple<int, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, int, int>;
@@ -89,7 +92,8 @@ struct Context {
     int cus = 0;
     int clock_khz = 0;
     char arch[64] = {0};
-    perm_tuning tuning{};
+    perm_tuning tunings[PERM_TUNE_CLASSES]{};
+    int32_t tune_src[PERM_TUNE_CLASSES]{};
     hipStream_t stream = nullptr;
     std::mutex mu;
 
@@ -114,7 +118,8 @@ struct Context {
     int last_graph = 0;
 
     ~Context();
-    int grid_blocks() const { return grid_blocks(tuning); }
+    const perm_tuning &tn(int cls) const { return tunings[cls]; }
+    void set_tuning(int cls, const perm_tuning &t, int32_t src);
     void drop_graphs();
     int32_t reserve_work(int32_t count, int64_t rows);
     int32_t join(hipStream_t st);
@@ -133,6 +138,13 @@ struct Context {
 };
 
 int32_t get_context(Context **out);
+
+// Tuning cache (perm3_tuning.hip): apply the lines of a cache file that match
+// the context's device (returns the classes set, or -1 if the file cannot be
+// read), and the load made when a context is created.
+int cache_apply(Context &c, const char *path);
+void load_default_cache(Context &c);
+extern const char *const TUNE_CLASS_NAMES[PERM_TUNE_CLASSES];
 bool timing_enabled();   // perm_timing_enable() state of the calling thread
 
 }  // namespace perm3

@@ -88,6 +88,14 @@ bool tuning_valid(const perm_tuning &t)
            t.max_tasks_log >= 0 && t.max_tasks_log <= 40;
 }
 
+int tune_class_host(int32_t count, int32_t n0)
+{
+    if (count != 1) return PERM_TUNE_BATCH;
+    if (n0 <= 24) return PERM_TUNE_SMALL;
+    if (n0 <= 31) return PERM_TUNE_MID;
+    return PERM_TUNE_LARGE;
+}
+
 // ------------------------------------------------------------------ context
 
 DevBuf::~DevBuf()
@@ -218,7 +226,12 @@ int32_t get_context(Context **out)
     c->cus = prop.multiProcessorCount;
     c->clock_khz = prop.clockRate;
     snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
-    c->tuning = default_tuning();
+    for (int k = 0; k < PERM_TUNE_CLASSES; ++k) {
+        c->tunings[k] = default_tuning();
+        c->tune_src[k] = PERM_TUNE_SRC_DEFAULT;
+    }
+    // a tuning cache beside the library (or named by the environment), if any
+    load_default_cache(*c);
     HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIP_TRY(hipEventCreate(&c->ev_walk0));
     HIP_TRY(hipEventCreate(&c->ev_walk1));
@@ -239,6 +252,13 @@ bool timing_enabled() { return tl_timing; }
 int Context::grid_blocks(const perm_tuning &tn) const
 {
     return cus * std::min(tn.waves_per_simd, walk_resident_per_cu(tn.states_per_lane));
+}
+
+void Context::set_tuning(int cls, const perm_tuning &t, int32_t src)
+{
+    tunings[cls] = t;
+    tune_src[cls] = src;
+    drop_graphs();
 }
 
 void Context::drop_graphs()
@@ -397,8 +417,9 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
     last_graph = 0;
     // Calls of up to SMALL_PLAN_MAX matrices are two launches, issued directly:
     // replaying them as a graph costs more than it saves.
-    if (timed || !use_graph || !tuning.use_graphs || L.count <= SMALL_PLAN_MAX) {
-        rc = enqueue(L, ws, tuning, st, timed);
+    const perm_tuning &tune = tn(L.cls);
+    if (timed || !use_graph || !tune.use_graphs || L.count <= SMALL_PLAN_MAX) {
+        rc = enqueue(L, ws, tune, st, timed);
         if (rc) return rc;
         return mark(st);
     }
@@ -416,7 +437,7 @@ int32_t Context::run(const Launch &L, hipStream_t st, bool use_graph)
         if (graphs.size() >= 32) drop_graphs();
         hipGraph_t g = nullptr;
         HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-        rc = enqueue(L, ws, tuning, st, false);
+        rc = enqueue(L, ws, tune, st, false);
         hipError_t e = hipStreamEndCapture(st, &g);
         if (rc) {
             if (g) (void)hipGraphDestroy(g);
@@ -458,7 +479,7 @@ int32_t Context::run_captured(const Launch &L, hipStream_t st)
     captured.push_back(std::move(buf));
     Launch C = L;
     C.zero_acc = L.count <= SMALL_PLAN_MAX ? 1 : 0;
-    const int32_t rc = enqueue(C, w, tuning, st, false);
+    const int32_t rc = enqueue(C, w, tn(L.cls), st, false);
     last_timing_valid = false;
     last_graph = 0;
     return rc;
@@ -473,7 +494,7 @@ int32_t Context::run_dev(const Launch &L, hipStream_t user)
 {
     if (user) return run(L, user, true);
     // a call launched directly (no graph capture) goes on the NULL stream itself
-    if (L.count <= SMALL_PLAN_MAX || !tuning.use_graphs) return run(L, nullptr, false);
+    if (L.count <= SMALL_PLAN_MAX || !tn(L.cls).use_graphs) return run(L, nullptr, false);
     HIP_TRY(hipEventRecord(ev_in, nullptr));
     HIP_TRY(hipStreamWaitEvent(stream, ev_in, 0));
     int32_t rc = run(L, stream, true);
@@ -502,9 +523,10 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     const size_t stage_bytes = ns_at + ns_bytes;
     // the orders are known here: a small call whose walk k_small takes alone
     // needs no k_walk after it (the kernel makes the same decision)
+    const int cls = tune_class_host(count, ns[0]);
     const bool fused_only = small_call_fused(ns, count, use_range);
     uint64_t tasks = 0;
-    if (fused_only) tasks = small_call_tasks(plan_args(ws, tuning, nullptr, count, nullptr, nullptr), ns, count);
+    if (fused_only) tasks = small_call_tasks(plan_args(ws, tn(cls), nullptr, count, nullptr, nullptr), ns, count);
     // Such a call reads its inputs straight from coherent pinned memory when
     // that moves little over the host link (each of its waves reads the
     // orders, the offsets and its matrix once): no staging copy before it.
@@ -553,8 +575,9 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     L.range_lo = lo;
     L.range_hi = hi;
     L.fused_only = fused_only ? 1 : 0;
+    L.cls = cls;
     // one wave per task (4 per block): blocks beyond the tasks would only start and leave
-    if (fused_only) L.small_blocks = (int32_t)std::min<uint64_t>((tasks + 3) / 4, (uint64_t)grid_blocks());
+    if (fused_only) L.small_blocks = (int32_t)std::min<uint64_t>((tasks + 3) / 4, (uint64_t)grid_blocks(tn(cls)));
     rc = run(L, st, false);
     if (rc) return rc;
     if (tally_host) HIP_TRY(hipMemcpyAsync(tally_host, ws.tally, sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -707,6 +730,7 @@ int32_t perm_mod3_batch_dev(const uint8_t *mats_dev, const int64_t *offs_dev, co
     L.count = count;
     L.out_dev = out_dev;
     L.hist_dev = hist_dev;
+    L.cls = count == 1 ? PERM_TUNE_LARGE : PERM_TUNE_BATCH;
     return run_device_call(L, stream);
 }
 
@@ -727,6 +751,7 @@ int32_t perm_mod3_batch_packed(const uint64_t *planes_dev, const int64_t *row_of
     L.count = count;
     L.out_dev = out_dev;
     L.hist_dev = hist_dev;
+    L.cls = count == 1 ? PERM_TUNE_LARGE : PERM_TUNE_BATCH;
     return run_device_call(L, stream);
 }
 
@@ -854,7 +879,8 @@ int32_t perm_mod3_census(int32_t n, int32_t generator, uint64_t key, uint64_t fi
             L.count = (int32_t)cnt;
             L.out_dev = out;
             L.hist_dev = (uint64_t *)dcounts;
-            if ((rc = c->enqueue(L, c->ws, c->tuning, st, false))) return rc;
+            L.cls = PERM_TUNE_BATCH;
+            if ((rc = c->enqueue(L, c->ws, c->tn(PERM_TUNE_BATCH), st, false))) return rc;
         }
     }
     uint64_t h[64 * 3];
@@ -874,7 +900,7 @@ int32_t perm_tuning_get(perm_tuning *t)
     int32_t rc = get_context(&c);
     if (rc) return rc;
     std::lock_guard<std::mutex> g(c->mu);
-    *t = c->tuning;
+    *t = c->tunings[PERM_TUNE_LARGE];
     return PERM_OK;
 }
 
@@ -886,8 +912,43 @@ int32_t perm_tuning_set(const perm_tuning *t)
     int32_t rc = get_context(&c);
     if (rc) return rc;
     std::lock_guard<std::mutex> g(c->mu);
-    c->tuning = *t;
-    c->drop_graphs();
+    for (int k = 0; k < PERM_TUNE_CLASSES; ++k) c->set_tuning(k, *t, PERM_TUNE_SRC_SET);
+    return PERM_OK;
+}
+
+int32_t perm_tuning_get_class(int32_t cls, perm_tuning *t, int32_t *source)
+{
+    if (!t) return set_error(PERM_EINVAL, "null pointer");
+    if (cls < 0 || cls >= PERM_TUNE_CLASSES) return set_error(PERM_EINVAL, "unknown tuning class %d", cls);
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    *t = c->tunings[cls];
+    if (source) *source = c->tune_src[cls];
+    return PERM_OK;
+}
+
+int32_t perm_tuning_set_class(int32_t cls, const perm_tuning *t)
+{
+    if (!t) return set_error(PERM_EINVAL, "null pointer");
+    if (cls < 0 || cls >= PERM_TUNE_CLASSES) return set_error(PERM_EINVAL, "unknown tuning class %d", cls);
+    if (!tuning_valid(*t)) return set_error(PERM_EINVAL, "tuning out of range");
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    c->set_tuning(cls, *t, PERM_TUNE_SRC_SET);
+    return PERM_OK;
+}
+
+int32_t perm_tuning_reset(void)
+{
+    Context *c = nullptr;
+    int32_t rc = get_context(&c);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> g(c->mu);
+    for (int k = 0; k < PERM_TUNE_CLASSES; ++k) c->set_tuning(k, default_tuning(), PERM_TUNE_SRC_DEFAULT);
     return PERM_OK;
 }
 

@@ -549,7 +549,7 @@ int32_t perm_server_create(const perm_server_cfg *cfg, perm_server **out)
     if (s->cfg.quantum == 0) s->cfg.quantum = 1ull << 33;
     {
         std::lock_guard<std::mutex> g(c->mu);
-        s->tuning = c->tuning;
+        s->tuning = c->tunings[PERM_TUNE_BATCH];
     }
     rc = s->init();
     if (rc) {

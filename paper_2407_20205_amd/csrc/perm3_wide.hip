@@ -235,8 +235,8 @@ extern "C" int32_t perm_mod3_range_tally_wide(const uint8_t *A, int32_t n, uint6
     int64_t *h_tally = (int64_t *)(h + h_tally_at);
     memcpy(h, A, mat_bytes);
 
-    const uint64_t resident = (uint64_t)c->cus * (uint64_t)std::min(c->tuning.waves_per_simd, wide_resident_per_cu());
-    WideArgs a = plan_wide(c->tuning, (int)(4 * resident), n, begin, count);
+    const uint64_t resident = (uint64_t)c->cus * (uint64_t)std::min(c->tn(PERM_TUNE_LARGE).waves_per_simd, wide_resident_per_cu());
+    WideArgs a = plan_wide(c->tn(PERM_TUNE_LARGE), (int)(4 * resident), n, begin, count);
     a.rows = (const RowX *)(d + rows_at);
     a.tally = (int64_t *)(d + tally_at);
     a.queue = (uint64_t *)(d + queue_at);

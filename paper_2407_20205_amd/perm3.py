@@ -39,6 +39,17 @@ PERM_F3_MAX_LEN = 1 << 40
 PERM_MAX_TALLIES = 1 << 20
 PERM_POLICY_SRPT = 0
 PERM_POLICY_FIFO = 1
+PERM_TUNE_SMALL = 0
+PERM_TUNE_MID = 1
+PERM_TUNE_LARGE = 2
+PERM_TUNE_BATCH = 3
+PERM_TUNE_CLASSES = 4
+TUNE_CLASS_NAMES = ("small", "mid", "large", "batch")
+PERM_TUNE_SRC_DEFAULT = 0
+PERM_TUNE_SRC_CACHE = 1
+PERM_TUNE_SRC_SET = 2
+PERM_TUNE_SRC_AUTOTUNE = 3
+TUNE_SOURCE_NAMES = ("default", "cache", "set", "autotune")
 
 
 class PermError(RuntimeError):
@@ -117,7 +128,13 @@ EXPORTS = [
     ("perm_server_destroy", _i32, [_vp]),
     ("perm_tuning_get", _i32, [_vp]),
     ("perm_tuning_set", _i32, [_vp]),
+    ("perm_tuning_get_class", _i32, [_i32, _vp, _vp]),
+    ("perm_tuning_set_class", _i32, [_i32, _vp]),
+    ("perm_tuning_reset", _i32, []),
+    ("perm_tuning_cache_load", _i32, [ctypes.c_char_p, _vp]),
+    ("perm_tuning_cache_save", _i32, [ctypes.c_char_p]),
     ("perm_autotune", _i32, [_i32, _i32, _vp]),
+    ("perm_autotune_batch", _i32, [_vp, _vp, _vp, _i32, _vp, _i32, _vp]),
     ("perm_timing_enable", _i32, [_i32]),
     ("perm_timing_last", _i32, [_vp]),
     ("perm_device_info_get", _i32, [_vp]),
@@ -373,9 +390,65 @@ def tuning_set(t: perm_tuning) -> None:
     _check(lib().perm_tuning_set(ctypes.addressof(t)))
 
 
+def tuning_get_class(cls: int) -> tuple[perm_tuning, int]:
+    """(tuning, source) of one tuning class (PERM_TUNE_*; source PERM_TUNE_SRC_*)."""
+    t = perm_tuning()
+    src = ctypes.c_int32(0)
+    _check(lib().perm_tuning_get_class(cls, ctypes.addressof(t), ctypes.addressof(src)))
+    return t, int(src.value)
+
+
+def tuning_set_class(cls: int, t: perm_tuning) -> None:
+    _check(lib().perm_tuning_set_class(cls, ctypes.addressof(t)))
+
+
+def tuning_reset() -> None:
+    """Every class back to the library's defaults."""
+    _check(lib().perm_tuning_reset())
+
+
+def tuning_cache_load(path: str) -> int:
+    """Apply the lines of a tuning cache file that match this device; returns the classes set."""
+    got = ctypes.c_int32(0)
+    _check(lib().perm_tuning_cache_load(os.fsencode(path), ctypes.addressof(got)))
+    return int(got.value)
+
+
+def tuning_cache_save(path: str) -> None:
+    _check(lib().perm_tuning_cache_save(os.fsencode(path)))
+
+
+class saved_tunings:
+    """Context manager: every class's tuning is put back on exit (a class not at the defaults then
+    reads as source PERM_TUNE_SRC_SET)."""
+
+    def __enter__(self):
+        self._saved = [tuning_get_class(k) for k in range(PERM_TUNE_CLASSES)]
+        return self
+
+    def __exit__(self, *exc):
+        # classes that held the defaults get them back with their source; the others are set
+        tuning_reset()
+        for k, (t, src) in enumerate(self._saved):
+            if src != PERM_TUNE_SRC_DEFAULT:
+                tuning_set_class(k, t)
+        return False
+
+
 def autotune(n: int, budget_ms: int = 20000) -> perm_tuning:
+    """Tune the class of a one-matrix host call of order n (12..63); see include/perm3.h."""
     t = perm_tuning()
     _check(lib().perm_autotune(n, budget_ms, ctypes.addressof(t)))
+    return t
+
+
+def autotune_batch(planes_dev, row_off_dev, ns_dev, out_dev, budget_ms: int = 60000) -> perm_tuning:
+    """Tune class PERM_TUNE_BATCH on a packed batch already on the GPU (as perm_mod3_batch_packed)."""
+    count = _check_batch_args(planes_dev, "planes_dev", _dtypes("int64", "uint64"), row_off_dev, "row_off_dev",
+                              ns_dev, out_dev, None)
+    t = perm_tuning()
+    _check(lib().perm_autotune_batch(_dptr(planes_dev), _dptr(row_off_dev), _dptr(ns_dev), count,
+                                     _dptr(out_dev), budget_ms, ctypes.addressof(t)))
     return t
 
 

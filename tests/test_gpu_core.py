@@ -236,8 +236,7 @@ def test_laplace_expansion_34():
 def test_tuning_does_not_change_tallies():
     A = W.uniform_matrix(33, 5)
     ref = P.perm_mod3_range_tally(A, 0, 1 << 33)
-    saved = P.tuning_get()
-    try:
+    with P.saved_tunings():
         for wps, bl, cl, tpw, dm, st in [(1, 4, 8, 1, 10, 1), (2, 6, 12, 4, 12, 2), (16, 5, 24, 64, 40, 4),
                                          (8, 4, 20, 8, 33, 2), (4, 5, 9, 2, 11, 4), (8, 6, 16, 16, 12, 1)]:
             t = P.perm_tuning()
@@ -247,23 +246,19 @@ def test_tuning_does_not_change_tallies():
             P.tuning_set(t)
             assert P.perm_mod3_range_tally(A, 0, 1 << 33) == ref, (wps, bl, cl, tpw, dm, st)
             assert P.perm_mod3_range_tally(A, 12345, 1 << 22) == oracle.range_tally(A, 12345, 1 << 22)
-    finally:
-        P.tuning_set(saved)
 
 
 def test_autotune_keeps_results():
     A = W.uniform_matrix(30, 123)
     ref = P.perm_mod3_range_tally(A, 0, 1 << 30)
-    saved = P.tuning_get()
-    try:
+    with P.saved_tunings():
         best = P.autotune(30, budget_ms=1500)
-        now = P.tuning_get()
-        assert best.as_dict() == now.as_dict()            # the winner becomes the context's tuning
+        now, src = P.tuning_get_class(P.PERM_TUNE_MID)     # n = 30: the class of 25..31
+        assert best.as_dict() == now.as_dict()            # the winner becomes the class's tuning
+        assert src == P.PERM_TUNE_SRC_AUTOTUNE
         assert 1 <= best.waves_per_simd <= 16 and best.body_log_mid in (4, 5, 6)
         assert P.perm_mod3_range_tally(A, 0, 1 << 30) == ref
         assert P.perm_mod3(A) == oracle.perm_mod3(A)
-    finally:
-        P.tuning_set(saved)
 
 
 def test_from_tallies_finishes_shards():

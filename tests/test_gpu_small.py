@@ -154,8 +154,7 @@ def test_states_per_lane(states):
     A = W.uniform_matrix(26, 4035)
     lo, hi = 12345, (1 << 25) + 777
     want_t = oracle.range_tally(A, lo, hi)
-    base = P.tuning_get()
-    try:
+    with P.saved_tunings():
         t = P.tuning_get()
         t.states_per_lane = states
         P.tuning_set(t)
@@ -164,8 +163,6 @@ def test_states_per_lane(states):
             assert np.array_equal(got, want)
             assert np.array_equal(P.perm_mod3_batch(mats), want)
             assert P.perm_mod3_range_tally(A, lo, hi) == want_t
-    finally:
-        P.tuning_set(base)
 
 
 def test_launch_counts():

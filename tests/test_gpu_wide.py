@@ -172,8 +172,7 @@ def test_wide_tuning_does_not_change_tallies():
     a = (1 << 99) + 4321
     ref_a = P.perm_mod3_range_tally_wide(A, a, 1 << 16)
     ref_b = P.perm_mod3_range_tally_wide(B, h << 20, 1 << 20)
-    saved = P.tuning_get()
-    try:
+    with P.saved_tunings():
         for bl, cl, tpw, dm, wps in [(4, 8, 1, 10, 1), (6, 12, 4, 12, 2), (5, 24, 64, 40, 16), (4, 9, 2, 11, 4)]:
             t = P.tuning_get()
             t.body_log, t.chunk_log_max, t.tasks_per_wave, t.direct_max_n, t.waves_per_simd = bl, cl, tpw, dm, wps
@@ -181,8 +180,6 @@ def test_wide_tuning_does_not_change_tallies():
             P.tuning_set(t)
             assert P.perm_mod3_range_tally_wide(A, a, 1 << 16) == ref_a
             assert P.perm_mod3_range_tally_wide(B, h << 20, 1 << 20) == ref_b
-    finally:
-        P.tuning_set(saved)
     assert ref_a == oracle.range_tally_wide(A, a, 1 << 16, threads=host_threads())
 
 
