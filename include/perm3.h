@@ -362,8 +362,10 @@ int32_t perm_tuning_set(const perm_tuning *t);
 /* One class's tuning and its source (source may be NULL). */
 int32_t perm_tuning_get_class(int32_t cls, perm_tuning *t, int32_t *source);
 int32_t perm_tuning_set_class(int32_t cls, const perm_tuning *t);
-/* Every class back to the built-in defaults (source PERM_TUNE_SRC_DEFAULT). */
-int32_t perm_tuning_reset(void);
+/* Every class back to the built-in defaults (source PERM_TUNE_SRC_DEFAULT);
+ * with with_cache != 0, then the tuning cache a new context loads (below),
+ * which leaves the classes as they were when the context was made. */
+int32_t perm_tuning_reset(int32_t with_cache);
 
 /*
  * Tuning cache: a text file, one line per (device, class):

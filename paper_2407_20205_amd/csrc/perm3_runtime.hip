@@ -942,13 +942,14 @@ int32_t perm_tuning_set_class(int32_t cls, const perm_tuning *t)
     return PERM_OK;
 }
 
-int32_t perm_tuning_reset(void)
+int32_t perm_tuning_reset(int32_t with_cache)
 {
     Context *c = nullptr;
     int32_t rc = get_context(&c);
     if (rc) return rc;
     std::lock_guard<std::mutex> g(c->mu);
     for (int k = 0; k < PERM_TUNE_CLASSES; ++k) c->set_tuning(k, default_tuning(), PERM_TUNE_SRC_DEFAULT);
+    if (with_cache) load_default_cache(*c);
     return PERM_OK;
 }
 

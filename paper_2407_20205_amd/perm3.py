@@ -130,7 +130,7 @@ EXPORTS = [
     ("perm_tuning_set", _i32, [_vp]),
     ("perm_tuning_get_class", _i32, [_i32, _vp, _vp]),
     ("perm_tuning_set_class", _i32, [_i32, _vp]),
-    ("perm_tuning_reset", _i32, []),
+    ("perm_tuning_reset", _i32, [_i32]),
     ("perm_tuning_cache_load", _i32, [ctypes.c_char_p, _vp]),
     ("perm_tuning_cache_save", _i32, [ctypes.c_char_p]),
     ("perm_autotune", _i32, [_i32, _i32, _vp]),
@@ -402,9 +402,10 @@ def tuning_set_class(cls: int, t: perm_tuning) -> None:
     _check(lib().perm_tuning_set_class(cls, ctypes.addressof(t)))
 
 
-def tuning_reset() -> None:
-    """Every class back to the library's defaults."""
-    _check(lib().perm_tuning_reset())
+def tuning_reset(with_cache: bool = False) -> None:
+    """Every class back to the library's defaults; with_cache: then the tuning cache a new context
+    loads, as when the context was made."""
+    _check(lib().perm_tuning_reset(1 if with_cache else 0))
 
 
 def tuning_cache_load(path: str) -> int:
@@ -419,18 +420,20 @@ def tuning_cache_save(path: str) -> None:
 
 
 class saved_tunings:
-    """Context manager: every class's tuning is put back on exit (a class not at the defaults then
-    reads as source PERM_TUNE_SRC_SET)."""
+    """Context manager: every class's tuning, and where it came from, put back on exit.  The
+    classes start again as a new context makes them (defaults, then the tuning cache); a class
+    whose saved values differ from that is set, and then reads as source PERM_TUNE_SRC_SET unless
+    it was that already."""
 
     def __enter__(self):
         self._saved = [tuning_get_class(k) for k in range(PERM_TUNE_CLASSES)]
         return self
 
     def __exit__(self, *exc):
-        # classes that held the defaults get them back with their source; the others are set
-        tuning_reset()
+        tuning_reset(with_cache=True)
         for k, (t, src) in enumerate(self._saved):
-            if src != PERM_TUNE_SRC_DEFAULT:
+            now, now_src = tuning_get_class(k)
+            if now.as_dict() != t.as_dict() or now_src != src:
                 tuning_set_class(k, t)
         return False
 

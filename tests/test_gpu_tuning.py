@@ -43,9 +43,14 @@ def check_results(b, want_b, singles):
 
 
 def test_classes_start_at_defaults_or_cache():
+    # every earlier test puts the tunings back as a new context makes them
     for t, src in all_classes():
         assert src in (P.PERM_TUNE_SRC_DEFAULT, P.PERM_TUNE_SRC_CACHE)
         assert 1 <= t.waves_per_simd <= 16
+    with P.saved_tunings():
+        P.tuning_set(P.tuning_get())
+        assert all(src == P.PERM_TUNE_SRC_SET for _, src in all_classes())
+    assert all(src in (P.PERM_TUNE_SRC_DEFAULT, P.PERM_TUNE_SRC_CACHE) for _, src in all_classes())
 
 
 def test_set_class_is_per_class():
