@@ -201,6 +201,37 @@ int32_t perm_mod3_batch_packed(const uint64_t *planes_dev, const int64_t *row_of
                                 uint64_t *hist_dev, void *stream);
 
 /*
+ * perm_mod3_batch_packed_noalloc: perm_mod3_batch_packed for callers that
+ * cannot allocate device memory: code recorded under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc.  Arguments, layout, results
+ * and the histogram are those of perm_mod3_batch_packed, and the same kernels
+ * run, but the call allocates nothing (no hipMalloc, hipFree, host staging or
+ * library graph): its work buffers (plan records, packed rows, tallies,
+ * completion counts, queue counters, accumulator words) live in one static
+ * device array of the library, PERM_NOALLOC_SCRATCH_BYTES bytes on every
+ * device the library runs on, held until the process ends.  The array's
+ * device address is looked up once per device when the library first runs
+ * there (that first call makes the device's context: a stream and events,
+ * no device memory).
+ *   count:  0 <= count <= PERM_NOALLOC_MAX_COUNT, else PERM_EINVAL and
+ *           nothing runs.
+ *   stream: the kernels go on `stream` (NULL: the legacy default stream)
+ *           directly; under the caller's graph capture they are recorded
+ *           into the caller's graph.  The call is not ordered with other
+ *           calls into the library (it shares no buffer with them).
+ * Every call on one device shares that device's array, which keeps the last
+ * call's contents; each call clears what must start at zero itself.  Two such
+ * calls that overlap on one device (different streams without an order
+ * between them, or replays of two graphs holding such calls run
+ * concurrently) race on the array and give wrong results: order them.
+ */
+#define PERM_NOALLOC_MAX_COUNT 8192
+#define PERM_NOALLOC_SCRATCH_BYTES 17212416ull
+int32_t perm_mod3_batch_packed_noalloc(const uint64_t *planes_dev, const int64_t *row_off_dev,
+                                       const int32_t *ns_dev, int32_t count, uint8_t *out_dev,
+                                       uint64_t *hist_dev, void *stream);
+
+/*
  * perm_mod3_from_tallies: perm(A) mod 3 of an n x n matrix from the exact
  * partial tallies T(a_k, b_k) of Gray ranges that together cover [0, 2^n)
  * exactly once (for example the shards of a long run, each from

@@ -10,7 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libperm3.so")
 SOURCES = ["perm3_kernels.hip", "perm3_census.hip", "perm3_wide.hip", "perm3_vec.hip", "perm3_runtime.hip",
-           "perm3_server.hip", "perm3_autotune.hip", "perm3_tuning.hip"]
+           "perm3_server.hip", "perm3_autotune.hip", "perm3_tuning.hip",
+           "perm3_noalloc.hip"]
 ARCH = "gfx950"
 
 

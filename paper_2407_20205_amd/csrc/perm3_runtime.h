@@ -12,6 +12,7 @@
 
 #include "perm3.h"
 #include "perm3_internal.h"
+#include "perm3_walk.hpp"
 
 namespace perm3 {
 
@@ -60,6 +61,26 @@ struct WorkSet {
     uint64_t *acc = nullptr;          // SMALL_PLAN_MAX
 };
 
+constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// The pieces of a work set, in order, each 256-byte aligned; off[9] is the total.
+struct WorkSetLayout {
+    size_t off[10];
+};
+
+constexpr WorkSetLayout workset_layout(int32_t count, int64_t rows, bool acc)
+{
+    const size_t c = (size_t)(count > 1 ? count : 1);
+    const size_t r = (size_t)(rows > 1 ? rows : 1);
+    const size_t sz[9] = {c * sizeof(MatMeta), c * sizeof(int32_t), (c + 1) * sizeof(uint64_t),
+                          c * sizeof(int64_t), c * sizeof(uint64_t), c, CNT_COUNT * sizeof(uint64_t),
+                          r * sizeof(RowW), acc ? SMALL_PLAN_MAX * sizeof(uint64_t) : 0};
+    WorkSetLayout L{};
+    L.off[0] = 0;
+    for (int i = 0; i < 9; ++i) L.off[i + 1] = L.off[i] + align256(sz[i]);
+    return L;
+}
+
 // Bytes of a work set for `count` matrices and `rows` rows in all (with the
 // accumulator words when `acc`), and its buffers carved from one block of at
 // least that many bytes (256-byte aligned pieces).
@@ -104,6 +125,7 @@ struct Context {
     int32_t ws_count = 0;
     int64_t ws_rows = 0;
     std::vector<std::unique_ptr<DevBuf>> captured;   // work sets of calls captured into callers' graphs
+    void *noalloc_scratch = nullptr;   // this device's address of the allocation-free calls' work set
     HostBuf h_stage, h_wide;
     HostBuf h_out;                   // host-call results, written by the kernels directly
     HostBuf h_zc{hipHostMallocCoherent};   // small host calls' inputs, read by the kernel directly
@@ -143,6 +165,10 @@ int32_t get_context(Context **out);
 // the context's device (returns the classes set, or -1 if the file cannot be
 // read), and the load made when a context is created.
 int cache_apply(Context &c, const char *path);
+
+// The device address of the allocation-free calls' static work set on the
+// context's device (perm3_noalloc.hip), looked up once when the context is made.
+int32_t noalloc_init(Context &c);
 void load_default_cache(Context &c);
 extern const char *const TUNE_CLASS_NAMES[PERM_TUNE_CLASSES];
 bool timing_enabled();   // perm_timing_enable() state of the calling thread

@@ -143,26 +143,6 @@ hipError_t HostBuf::reserve(size_t n)
     return e;
 }
 
-static constexpr size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// The pieces of a work set, in order, each 256-byte aligned.
-struct WorkSetLayout {
-    size_t off[10];
-};
-
-static constexpr WorkSetLayout workset_layout(int32_t count, int64_t rows, bool acc)
-{
-    const size_t c = (size_t)(count > 1 ? count : 1);
-    const size_t r = (size_t)(rows > 1 ? rows : 1);
-    const size_t sz[9] = {c * sizeof(MatMeta), c * sizeof(int32_t), (c + 1) * sizeof(uint64_t),
-                          c * sizeof(int64_t), c * sizeof(uint64_t), c, CNT_COUNT * sizeof(uint64_t),
-                          r * sizeof(RowW), acc ? SMALL_PLAN_MAX * sizeof(uint64_t) : 0};
-    WorkSetLayout L{};
-    L.off[0] = 0;
-    for (int i = 0; i < 9; ++i) L.off[i + 1] = L.off[i] + align256(sz[i]);
-    return L;
-}
-
 size_t workset_bytes(int32_t count, int64_t rows, bool acc) { return workset_layout(count, rows, acc).off[9]; }
 
 WorkSet workset_carve(void *base, int32_t count, int64_t rows, bool acc)
@@ -232,6 +212,8 @@ int32_t get_context(Context **out)
     }
     // a tuning cache beside the library (or named by the environment), if any
     load_default_cache(*c);
+    int32_t rc = noalloc_init(*c);
+    if (rc) return rc;
     HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     HIP_TRY(hipEventCreate(&c->ev_walk0));
     HIP_TRY(hipEventCreate(&c->ev_walk1));

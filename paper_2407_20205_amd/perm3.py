@@ -37,6 +37,8 @@ PERM_F3_DIV = 3
 PERM_F3_NEG = 4
 PERM_F3_MAX_LEN = 1 << 40
 PERM_MAX_TALLIES = 1 << 20
+PERM_NOALLOC_MAX_COUNT = 8192
+PERM_NOALLOC_SCRATCH_BYTES = 17212416
 PERM_POLICY_SRPT = 0
 PERM_POLICY_FIFO = 1
 PERM_TUNE_SMALL = 0
@@ -118,6 +120,7 @@ EXPORTS = [
     ("perm_mod3_batch", _i32, [_vp, _vp, _i32, _vp]),
     ("perm_mod3_batch_dev", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     ("perm_mod3_batch_packed", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
+    ("perm_mod3_batch_packed_noalloc", _i32, [_vp, _vp, _vp, _i32, _vp, _vp, _vp]),
     ("perm_mod3_from_tallies", _i32, [_i32, _vp, _i32, _vp]),
     ("perm_mod3_pack", _i32, [_vp, _i32, _vp]),
     ("perm_mod3_census", _i32, [_i32, _i32, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, _vp]),
@@ -319,6 +322,15 @@ def perm_mod3_batch_packed(planes_dev, row_off_dev, ns_dev, out_dev, hist_dev=No
                               ns_dev, out_dev, hist_dev)
     _check(lib().perm_mod3_batch_packed(_dptr(planes_dev), _dptr(row_off_dev), _dptr(ns_dev), count,
                                         _dptr(out_dev), _dptr(hist_dev), _stream(stream)))
+
+
+def perm_mod3_batch_packed_noalloc(planes_dev, row_off_dev, ns_dev, out_dev, hist_dev=None, stream=None) -> None:
+    """perm_mod3_batch_packed with the library's static work set: allocates no device memory;
+    at most PERM_NOALLOC_MAX_COUNT matrices; overlapping calls on one GPU race (include/perm3.h)."""
+    count = _check_batch_args(planes_dev, "planes_dev", _dtypes("int64", "uint64"), row_off_dev, "row_off_dev",
+                              ns_dev, out_dev, hist_dev)
+    _check(lib().perm_mod3_batch_packed_noalloc(_dptr(planes_dev), _dptr(row_off_dev), _dptr(ns_dev), count,
+                                                _dptr(out_dev), _dptr(hist_dev), _stream(stream)))
 
 
 # ---------------------------------------------------------------- vectors over F_3 (device tensors)
