@@ -301,6 +301,10 @@ typedef struct {
                                in batches of up to 64 (and 2^28 Gray indices) beside
                                the tick in flight, one launch each; 0 = library
                                default (28), -1 = none, else 1..28               */
+    int32_t  tick_timeout_ms; /* watchdog: a tick still running after this many ms
+                               fails the server, and every request it holds or has
+                               queued completes with status PERM_EDEVICE; 0 = none */
+    int32_t  reserved;      /* 0 */
 } perm_server_cfg;
 
 #define PERM_POLICY_SRPT 0   /* least remaining work first                         */

@@ -42,16 +42,6 @@ struct WalkArgs {
     uint64_t *hist;
 };
 
-// Serving: one tick visits an explicit list of tasks over device-resident slots.
-struct TickTask {
-    int32_t slot;
-    int32_t m;            // chunk log
-    int32_t mode;         // WalkMode (FAST or DIRECT)
-    int32_t nchunks;      // valid chunks in this task (1..64)
-    uint64_t c_first;     // first chunk of this task
-    int32_t ul;           // log2 of the unrolled block
-    int32_t pad;
-};
 
 struct SlotInfo {
     int32_t n;

@@ -38,6 +38,17 @@ struct MatMeta {
     uint64_t c_first;   // first chunk index (lo >> m)
 };
 
+// Serving: one tick visits an explicit list of tasks over device-resident slots.
+struct TickTask {
+    int32_t slot;
+    int32_t m;            // chunk log
+    int32_t mode;         // WalkMode (FAST or DIRECT)
+    int32_t nchunks;      // valid chunks in this task (1..64)
+    uint64_t c_first;     // first chunk of this task
+    int32_t ul;           // log2 of the unrolled block
+    int32_t pad;
+};
+
 // counters[] slots
 enum : int { CNT_QUEUE = 0, CNT_TOTAL_TASKS = 1, CNT_COUNT = 4 };
 

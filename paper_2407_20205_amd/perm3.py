@@ -64,7 +64,8 @@ class PermError(RuntimeError):
 class perm_server_cfg(ctypes.Structure):
     _fields_ = [("max_slots", ctypes.c_int32), ("queue_cap", ctypes.c_int32),
                 ("work_budget", ctypes.c_uint64), ("quantum", ctypes.c_uint64),
-                ("policy", ctypes.c_int32), ("fast_max_n", ctypes.c_int32)]
+                ("policy", ctypes.c_int32), ("fast_max_n", ctypes.c_int32),
+                ("tick_timeout_ms", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class perm_done(ctypes.Structure):
@@ -505,10 +506,13 @@ class Server:
     """perm_server_*: continuous-batching request loop (C++ worker thread)."""
 
     def __init__(self, max_slots: int = 4096, queue_cap: int = 1 << 16, work_budget: int = 0,
-                 quantum: int = 0, policy: int = PERM_POLICY_SRPT, fast_max_n: int = 0):
+                 quantum: int = 0, policy: int = PERM_POLICY_SRPT, fast_max_n: int = 0,
+                 tick_timeout_ms: int = 0):
         """fast_max_n: requests of order <= fast_max_n run in one-launch batches beside the tick
-        (0: the library default, -1: none)."""
-        cfg = perm_server_cfg(max_slots, queue_cap, work_budget, quantum, policy, fast_max_n)
+        (0: the library default, -1: none).  tick_timeout_ms: a tick running longer fails the
+        server and every request it holds (0: no limit)."""
+        cfg = perm_server_cfg(max_slots, queue_cap, work_budget, quantum, policy, fast_max_n,
+                              tick_timeout_ms, 0)
         h = ctypes.c_void_p(None)
         _check(lib().perm_server_create(ctypes.addressof(cfg), ctypes.addressof(h)))
         self._h = h
