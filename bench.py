@@ -229,6 +229,38 @@ def bench_batch(P, W, torch, reps, baseline=True):
     return result
 
 
+def bench_batch_classes(P, W, torch, reps=5):
+    """The batch workload split by order: the matrices of each n (12..28) as a batch of their own,
+    timed by the library's HIP events (walk kernel, and all launches of the call), median of reps."""
+    b = W.batch_uniform()
+    dev = torch.device("cuda", 0)
+    rows = []
+    P.timing_enable(True)
+    try:
+        for n in range(12, 29):
+            mats = [M for M, k in zip(b.mats, b.ns) if int(k) == n]
+            planes = np.concatenate([P.perm_mod3_pack(M) for M in mats]).view(np.int64)
+            row_off = (np.arange(len(mats), dtype=np.int64) * n)
+            pl = torch.from_numpy(planes).to(dev)
+            ro = torch.from_numpy(row_off).to(dev)
+            ns = torch.full((len(mats),), n, dtype=torch.int32, device=dev)
+            out = torch.zeros(len(mats), dtype=torch.uint8, device=dev)
+            hot, tot = [], []
+            for _ in range(reps + 1):
+                P.perm_mod3_batch_packed(pl, ro, ns, out, None, None)
+                t = P.timing_last()
+                hot.append(t.hot_kernel_ms)
+                tot.append(t.total_ms)
+            terms = len(mats) * ((1 << n) - 1)
+            walk_ms = float(np.median(hot[1:]))
+            rows.append({"n": n, "count": len(mats), "walk_ms": walk_ms, "call_ms": float(np.median(tot[1:])),
+                         "terms_per_s": terms / walk_ms * 1e3})
+            log(f"batch class n={n}: {len(mats)} matrices, walk {walk_ms:.3f} ms, {rows[-1]['terms_per_s']:.3e} terms/s")
+    finally:
+        P.timing_enable(False)
+    return {"workload": "the 8192-matrix batch split by n, each order as its own batch", "rows": rows}
+
+
 # ------------------------------------------------------------------ single 20 x 20 (latency)
 
 def bench_single20(P, W, torch, reps=200):
@@ -630,8 +662,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--only", choices=["headline", "single20", "batch", "serve", "large", "wide", "vec", "pi50",
-                                       "montecarlo", "census"],
+    ap.add_argument("--only", choices=["headline", "single20", "batch", "batch-classes", "serve", "large", "wide",
+                                       "vec", "pi50", "montecarlo", "census"],
                     default=None)
     ap.add_argument("--mc-scale", type=float, default=0.01, help="fraction of Table 4's trial counts")
     ap.add_argument("--mc-n", default="6-30", help="range of n for the Monte Carlo study, e.g. 6-17")
@@ -735,6 +767,8 @@ def main():
         log("vec: " + ", ".join(f"{k} {vc[k]['GB_per_s']:.0f} GB/s" for k in ("pack", "add", "mul", "dot", "unpack")) +
             f"; device copy {vc['device_copy_GB_per_s']:.0f} GB/s")
         line["vec"] = vc
+    if args.only == "batch-classes":
+        line["batch_classes"] = bench_batch_classes(P, W, torch)
     if args.only == "montecarlo":
         lo, hi = (int(x) for x in args.mc_n.split("-"))
         line["montecarlo"] = bench_montecarlo(P, args.mc_scale, lo, hi)

@@ -439,14 +439,25 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
     const uint64_t total = a.counters[CNT_TOTAL_TASKS];
     const uint32_t nwaves = gridDim.x * (WALK_BLOCK / 64);
     const cptr<uint64_t> task_start = to_const(a.task_start);
+    // A wave's tasks come in increasing order (its own index first, then the
+    // queue's), so the position holding the next task is at or after the
+    // last one: gallop forward from there, then bisect.
+    int pos = 0;
     for (uint64_t tau = wave_index(); tau < total; tau = next_task64(&a.counters[CNT_QUEUE], nwaves, lane)) {
         // position p in the order whose tasks contain tau: the largest p with
         // task_start[p] <= tau (matrices without tasks share their successor's start)
-        int lo = 0, hi = a.count;
+        int lo = pos, hi = pos + 1, step = 1;
+        while (hi < a.count && task_start[hi] <= tau) {
+            lo = hi;
+            hi = lo + step;
+            step <<= 1;
+        }
+        if (hi > a.count) hi = a.count;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
             if (task_start[mid] <= tau) lo = mid; else hi = mid;
         }
+        pos = lo;
         const int k = to_const(a.order)[lo];
         const MatMeta mt = load_const(a.meta, k);
         const uint64_t q = tau - task_start[lo];
