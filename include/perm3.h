@@ -360,7 +360,11 @@ typedef struct {
     int32_t min_task_log;     /* ... unless its tasks would then exceed 2^min_task_log Gray
                                  indices; each task ends with an atomic on its matrix's
                                  counters, and on one address those serialise (0..30)       */
-    int32_t reserved[1];
+    int32_t queue_task_log;   /* tasks of a call hold at least 2^queue_task_log Gray indices
+                                 once its work gives every persistent wave one such task:
+                                 each task after a wave's first is one atomic on the call's
+                                 single queue counter, and those serialise (0..30; 0 = no
+                                 floor)                                                      */
 } perm_tuning;
 
 /*

@@ -67,6 +67,7 @@ struct PlanArgs {
     int32_t states_log;           // log2 of the chunks a lane carries side by side
     int32_t max_tasks_log;        // at most 2^max_tasks_log tasks per matrix ...
     int32_t min_task_log;         // ... unless tasks would exceed 2^min_task_log indices
+    int32_t queue_task_log;       // floor of a task, once every wave has one that long (0: none)
     int32_t waves_total, tasks_per_wave;
     MatMeta *meta;
     int32_t *order;               // [count] matrix index by decreasing n
@@ -91,11 +92,21 @@ PERM3_HD inline void range_of(const PlanArgs &a, int n, uint64_t &lo, uint64_t &
 }
 
 // Chunk log that gives each persistent wave about tasks_per_wave tasks of the
-// whole call's work.
+// whole call's work, but tasks of at least 2^queue_task_log indices while that
+// still gives every wave a task (else one task per wave): every task after a
+// wave's first costs one atomic on the call's queue counter, and atomics on
+// one address serialise, so short tasks in large numbers would wait on it.
 PERM3_HD inline int target_chunk_log(const PlanArgs &a, double total_work)
 {
-    const double want_tasks = (double)a.waves_total * (double)(a.tasks_per_wave > 0 ? a.tasks_per_wave : 1);
-    const double per_task = total_work / want_tasks;
+    const double waves = (double)(a.waves_total > 0 ? a.waves_total : 1);
+    const double want_tasks = waves * (double)(a.tasks_per_wave > 0 ? a.tasks_per_wave : 1);
+    double per_task = total_work / want_tasks;
+    if (a.queue_task_log > 0) {
+        const double floor_task = (double)(1ull << a.queue_task_log);
+        const double one_each = total_work / waves;
+        const double lo = floor_task < one_each ? floor_task : one_each;
+        if (per_task < lo) per_task = lo;
+    }
     if (per_task < 128.0) return 0;
     return (63 - __builtin_clzll((uint64_t)per_task)) - 6 - a.states_log;
 }

@@ -73,6 +73,7 @@ perm_tuning default_tuning()
     t.mid_max_n = 31;
     t.max_tasks_log = 10;
     t.min_task_log = 19;
+    t.queue_task_log = 18;
     return t;
 }
 
@@ -85,7 +86,7 @@ bool tuning_valid(const perm_tuning &t)
            (t.states_per_lane == 1 || t.states_per_lane == 2 || t.states_per_lane == 4) &&
            t.body_log_mid >= 4 && t.body_log_mid <= 6 && t.mid_max_n >= 0 && t.mid_max_n <= 63 &&
            t.direct_max_n >= t.body_log_mid + 6 && t.min_task_log >= 0 && t.min_task_log <= 30 &&
-           t.max_tasks_log >= 0 && t.max_tasks_log <= 40;
+           t.max_tasks_log >= 0 && t.max_tasks_log <= 40 && t.queue_task_log >= 0 && t.queue_task_log <= 30;
 }
 
 int tune_class_host(int32_t count, int32_t n0)
@@ -302,6 +303,7 @@ PlanArgs Context::plan_args(const WorkSet &w, const perm_tuning &tn, const int32
     a.states_log = tn.states_per_lane == 4 ? 2 : (tn.states_per_lane == 2 ? 1 : 0);
     a.max_tasks_log = tn.max_tasks_log;
     a.min_task_log = tn.min_task_log;
+    a.queue_task_log = tn.queue_task_log;
     a.waves_total = 4 * grid_blocks(tn);
     a.tasks_per_wave = tn.tasks_per_wave;
     a.meta = w.meta;

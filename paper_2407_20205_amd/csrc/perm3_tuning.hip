@@ -36,7 +36,7 @@ const Field FIELDS[] = {
     {"direct_max_n", &perm_tuning::direct_max_n},     {"use_graphs", &perm_tuning::use_graphs},
     {"states_per_lane", &perm_tuning::states_per_lane}, {"body_log_mid", &perm_tuning::body_log_mid},
     {"mid_max_n", &perm_tuning::mid_max_n},           {"max_tasks_log", &perm_tuning::max_tasks_log},
-    {"min_task_log", &perm_tuning::min_task_log},
+    {"min_task_log", &perm_tuning::min_task_log},     {"queue_task_log", &perm_tuning::queue_task_log},
 };
 
 int class_of_name(const std::string &s)

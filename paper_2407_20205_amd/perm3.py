@@ -88,10 +88,10 @@ class perm_tuning(ctypes.Structure):
                 ("direct_max_n", ctypes.c_int32), ("use_graphs", ctypes.c_int32),
                 ("states_per_lane", ctypes.c_int32), ("body_log_mid", ctypes.c_int32),
                 ("mid_max_n", ctypes.c_int32), ("max_tasks_log", ctypes.c_int32),
-                ("min_task_log", ctypes.c_int32), ("reserved", ctypes.c_int32 * 1)]
+                ("min_task_log", ctypes.c_int32), ("queue_task_log", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class perm_timing(ctypes.Structure):

@@ -73,6 +73,35 @@ def test_small_call_decision_does_not_wrap(harness):
 
 # ---------------------------------------------------------------- plan
 
+def test_target_chunk_log_and_queue_floor(harness):
+    """A task (64 lanes x 2^m indices x S chunks) holds the call's work over waves x tasks_per_wave
+    tasks, but at least 2^queue_task_log indices while the work still gives every wave one such task
+    (else the work over the waves): the chunk log is the floor of log2 of that, less 6 and log2 S."""
+    g = W.rng(9)
+    cases = []
+    for _ in range(400):
+        work = float(int(g.integers(1, 1 << 40)))
+        waves = int(g.choice([1, 64, 1024, 6144, 8192]))
+        tpw = int(g.integers(1, 65))
+        slog = int(g.integers(0, 3))
+        q = int(g.choice([0, 12, 18, 20]))
+        cases.append((work, waves, tpw, slog, q))
+    cases += [(2.0 ** 36, 8192, 16, 0, 18), (2.0 ** 36, 6144, 32, 0, 18), (2.567e11, 8192, 32, 0, 18),
+              (8.1e9, 8192, 32, 0, 18), (8.1e9, 8192, 32, 0, 0), (100.0, 8192, 16, 0, 18)]
+    out = harness([f"target {w!r} {wv} {t} {s} {q}" for w, wv, t, s, q in cases])
+    for (work, waves, tpw, slog, q), line in zip(cases, out):
+        per_task = work / (waves * tpw)
+        if q:
+            per_task = max(per_task, min(2.0 ** q, work / waves))
+        want = 0 if per_task < 128 else int(np.floor(np.log2(np.floor(per_task)))) - 6 - slog
+        assert int(line) == want, (work, waves, tpw, slog, q)
+    # the 36x36 and the Monte Carlo batch are not changed by the floor; an order-24 batch alone is
+    by_case = dict(zip(cases, out))
+    assert int(by_case[(2.0 ** 36, 8192, 16, 0, 18)]) == 13
+    assert int(by_case[(2.567e11, 8192, 32, 0, 18)]) == 13
+    assert int(by_case[(8.1e9, 8192, 32, 0, 18)]) == 12 and int(by_case[(8.1e9, 8192, 32, 0, 0)]) == 8
+
+
 def test_plan_covers_the_range(harness):
     g = W.rng(8)
     cases, meta = [], []

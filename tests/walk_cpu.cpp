@@ -8,6 +8,7 @@
 // (Section 2).  Commands come one per line on stdin and each prints one line:
 //
 //   fused <count> <n_1> .. <n_count>        -> <fused 0/1> <capped work>
+//   target <work> <waves> <tasks_per_wave> <states_log> <queue_task_log> -> target chunk log
 //   plan <n> <lo> <hi> <target_m> <tuning 10 ints> -> <mode> <m> <ul> <c_first> <ntasks>
 //   chunks <UL> <S> <n> <m> <c> <digits>    -> T over chunks c + 64 q, q < S (walk_chunks_fast)
 //   direct <n> <m> <c> <digits>             -> T over chunk c (walk_chunk_direct)
@@ -173,6 +174,12 @@ int main()
             for (int k = 0; k < count; ++k) in >> ns[k];
             printf("%d %llu\n", small_call_fused(ns.data(), count, false) ? 1 : 0,
                    (unsigned long long)capped_work(ns.data(), count, SMALL_FUSED_WORK));
+        } else if (cmd == "target") {
+            double work = 0;
+            PlanArgs a;
+            memset(&a, 0, sizeof a);
+            in >> work >> a.waves_total >> a.tasks_per_wave >> a.states_log >> a.queue_task_log;
+            printf("%d\n", target_chunk_log(a, work));
         } else if (cmd == "plan") {
             int n, target_m;
             unsigned long long lo, hi;
