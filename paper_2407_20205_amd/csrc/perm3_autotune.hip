@@ -248,6 +248,7 @@ extern "C" int32_t perm_autotune_batch(const uint64_t *planes_dev, const int64_t
     L.count = count;
     L.out_dev = out_dev;
     L.cls = PERM_TUNE_BATCH;
+    L.defer = 1;
     const bool timing_was = timing_enabled();
     perm_timing_enable(1);
     // timed calls run eagerly on the library stream (no graph), all launches between two events

@@ -78,7 +78,8 @@ hipError_t launch_small(const PlanArgs &a, const PackU8Args &pk, const PackPlane
                         int kind, bool allow_fused, int blocks, hipStream_t st);
 hipError_t launch_pack_u8(const PackU8Args &a, hipStream_t st);
 hipError_t launch_pack_planes(const PackPlanesArgs &a, hipStream_t st);
-hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st);
+// defer: candidate blocks re-walked one lane each after a chunk (batches), else at once
+hipError_t launch_walk(const WalkArgs &a, int states, bool defer, int grid_blocks, hipStream_t st);
 hipError_t launch_tick(const TickArgs &a, int grid_blocks, hipStream_t st);
 int walk_resident_per_cu(int states);   // k_walk<states> workgroups per CU at once; 0: k_tick
 hipError_t launch_finish(const FinishArgs &a, int max_fin, hipStream_t st);

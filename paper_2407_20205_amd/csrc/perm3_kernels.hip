@@ -36,7 +36,7 @@ __device__ __forceinline__ Masks masks_for(int n)
 }
 
 // Walk one lane's chunk c (chunk length 2^m) clipped to [lo, hi).
-template <int UL, typename RP>
+template <int UL, bool DEFER, typename RP>
 __device__ __forceinline__ int walk_lane(RP R, int n, int m, int mode, uint64_t c,
                                          uint64_t lo, uint64_t hi, const StaticRows<UL> &sr)
 {
@@ -47,7 +47,7 @@ __device__ __forceinline__ int walk_lane(RP R, int n, int m, int mode, uint64_t 
     const uint64_t e = e0 < hi ? e0 : hi;
     if (a >= e) return 0;
     if (a == a0 && e == e0) {
-        if (mode == MODE_FAST) return walk_chunks_fast<UL, 1>(R, n, m, c, mk, sr);
+        if (mode == MODE_FAST) return walk_chunks_fast<UL, 1, DEFER>(R, n, m, c, mk, sr);
         return n > 32 ? walk_chunk_direct<true>(R, n, m, c, mk) : walk_chunk_direct<false>(R, n, m, c, mk);
     }
     return n > 32 ? walk_range_direct<true>(R, n, a, e, mk) : walk_range_direct<false>(R, n, a, e, mk);
@@ -55,7 +55,7 @@ __device__ __forceinline__ int walk_lane(RP R, int n, int m, int mode, uint64_t 
 
 // Walk a lane's S chunks c + 64 s, s = 0 .. S-1, clipped to [lo, hi): side by
 // side when all are whole fast-mode chunks, else one after another.
-template <int UL, int S, typename RP>
+template <int UL, int S, bool DEFER, typename RP>
 __device__ __forceinline__ int walk_lane_states(RP R, int n, int m, int mode, uint64_t c,
                                                 uint64_t lo, uint64_t hi, const StaticRows<UL> &sr)
 {
@@ -66,11 +66,11 @@ __device__ __forceinline__ int walk_lane_states(RP R, int n, int m, int mode, ui
             const uint64_t a0 = (c + 64u * (uint64_t)q) << m;
             whole &= a0 >= lo && a0 + (1ull << m) <= hi;
         }
-        if (whole) return walk_chunks_fast<UL, S>(R, n, m, c, masks_for(n), sr);
+        if (whole) return walk_chunks_fast<UL, S, DEFER>(R, n, m, c, masks_for(n), sr);
     }
     int tally = 0;
 #pragma unroll
-    for (int q = 0; q < S; ++q) tally += walk_lane<UL>(R, n, m, mode, c + 64u * (uint64_t)q, lo, hi, sr);
+    for (int q = 0; q < S; ++q) tally += walk_lane<UL, DEFER>(R, n, m, mode, c + 64u * (uint64_t)q, lo, hi, sr);
     return tally;
 }
 
@@ -423,16 +423,20 @@ __device__ void pack_small_planes(const PlanArgs &a, const PackPlanesArgs &pp, i
 
 // ------------------------------------------------------------------ walk
 
-// One task of one matrix: the lane's S chunks, with the matrix's block length.
-template <int UL, int S, typename RP>
+// One task of one matrix: the lane's S chunks, with the matrix's block length;
+// candidate blocks re-walked together after each chunk (DEFER) or each at once.
+template <int UL, int S, bool DEFER, typename RP>
 __device__ __forceinline__ int walk_task(RP R, const MatMeta &mt, uint64_t c)
 {
     StaticRows<UL> sr;
     if (mt.mode == MODE_FAST) load_static_rows<UL>(R, sr);
-    return walk_lane_states<UL, S>(R, mt.n, mt.m, mt.mode, c, mt.lo, mt.hi, sr);
+    return walk_lane_states<UL, S, DEFER>(R, mt.n, mt.m, mt.mode, c, mt.lo, mt.hi, sr);
 }
 
-template <int S>
+// DEFER: candidate blocks noted and re-walked one lane each (batches, whose
+// small matrices hold candidates in one block of tens), else re-walked by the
+// whole wave at once (one large matrix, where they are rare: the leaner walk).
+template <int S, bool DEFER>
 __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
 {
     const int lane = threadIdx.x & 63;
@@ -467,11 +471,11 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
             const cptr<RowW> R = to_const(a.rows) + mt.row_base;
             const uint64_t c = mt.c_first + q * (64u * S) + (uint64_t)lane;
             if (mt.ul == 4)
-                tally = walk_task<4, S>(R, mt, c);
+                tally = walk_task<4, S, DEFER>(R, mt, c);
             else if (mt.ul == 6)
-                tally = walk_task<6, S>(R, mt, c);
+                tally = walk_task<6, S, DEFER>(R, mt, c);
             else
-                tally = walk_task<5, S>(R, mt, c);
+                tally = walk_task<5, S, DEFER>(R, mt, c);
         }
         const int sum = wave_sum(tally);
 
@@ -652,11 +656,11 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk,
         if (!bad) {
             const uint64_t c = m.c_first + q * 64u + (uint64_t)lane;
             if (m.ul == 4)
-                tally = walk_task<4, 1>(R, m, c);
+                tally = walk_task<4, 1, true>(R, m, c);
             else if (m.ul == 6)
-                tally = walk_task<6, 1>(R, m, c);
+                tally = walk_task<6, 1, true>(R, m, c);
             else
-                tally = walk_task<5, 1>(R, m, c);
+                tally = walk_task<5, 1, true>(R, m, c);
         }
         const int sum = wave_sum(tally);
         if (lane == 0) {
@@ -713,11 +717,11 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_tick(TickArgs a)
         if (lane < tk.nchunks) {
             const uint64_t c = tk.c_first + (uint64_t)lane;
             if (tk.ul == 4)
-                tally = walk_task<4, 1>(R, mt, c);
+                tally = walk_task<4, 1, true>(R, mt, c);
             else if (tk.ul == 6)
-                tally = walk_task<6, 1>(R, mt, c);
+                tally = walk_task<6, 1, true>(R, mt, c);
             else
-                tally = walk_task<5, 1>(R, mt, c);
+                tally = walk_task<5, 1, true>(R, mt, c);
         }
         const int sum = wave_sum(tally);
         if (lane == 0 && sum != 0)
@@ -843,23 +847,29 @@ static int resident_per_cu(std::atomic<int> &cache, K kernel)
     return n;
 }
 
+// the fewer of the two forms (with and without deferred re-walks), so that a
+// plan made for the grid holds for either
 int walk_resident_per_cu(int states)
 {
-    static std::atomic<int> c1{0}, c2{0}, c4{0}, ct{0};
+    static std::atomic<int> c1{0}, c2{0}, c4{0}, d1{0}, d2{0}, d4{0}, ct{0};
     switch (states) {
-    case 1: return resident_per_cu(c1, k_walk<1>);
-    case 2: return resident_per_cu(c2, k_walk<2>);
-    case 4: return resident_per_cu(c4, k_walk<4>);
+    case 1: return std::min(resident_per_cu(c1, k_walk<1, false>), resident_per_cu(d1, k_walk<1, true>));
+    case 2: return std::min(resident_per_cu(c2, k_walk<2, false>), resident_per_cu(d2, k_walk<2, true>));
+    case 4: return std::min(resident_per_cu(c4, k_walk<4, false>), resident_per_cu(d4, k_walk<4, true>));
     default: return resident_per_cu(ct, k_tick);   // 0: the serving tick
     }
 }
 
-hipError_t launch_walk(const WalkArgs &a, int states, int grid_blocks, hipStream_t st)
+hipError_t launch_walk(const WalkArgs &a, int states, bool defer, int grid_blocks, hipStream_t st)
 {
-    switch (states) {
-    case 1: hipLaunchKernelGGL((k_walk<1>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
-    case 2: hipLaunchKernelGGL((k_walk<2>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
-    case 4: hipLaunchKernelGGL((k_walk<4>), dim3(grid_blocks), dim3(WALK_BLOCK), 0, st, a); break;
+    const dim3 g(grid_blocks), b(WALK_BLOCK);
+    switch (states * 2 + (defer ? 1 : 0)) {
+    case 2: hipLaunchKernelGGL((k_walk<1, false>), g, b, 0, st, a); break;
+    case 3: hipLaunchKernelGGL((k_walk<1, true>), g, b, 0, st, a); break;
+    case 4: hipLaunchKernelGGL((k_walk<2, false>), g, b, 0, st, a); break;
+    case 5: hipLaunchKernelGGL((k_walk<2, true>), g, b, 0, st, a); break;
+    case 8: hipLaunchKernelGGL((k_walk<4, false>), g, b, 0, st, a); break;
+    case 9: hipLaunchKernelGGL((k_walk<4, true>), g, b, 0, st, a); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

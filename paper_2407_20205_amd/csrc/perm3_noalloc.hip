@@ -87,6 +87,7 @@ extern "C" int32_t perm_mod3_batch_packed_noalloc(const uint64_t *planes_dev, co
     L.out_dev = out_dev;
     L.hist_dev = hist_dev;
     L.cls = count == 1 ? PERM_TUNE_LARGE : PERM_TUNE_BATCH;
+    L.defer = count > 1 ? 1 : 0;
     // the one-launch path's accumulator words must start at zero: a fill kernel clears them
     // (the plan kernel of a larger call clears its own tallies, counts and queue)
     L.zero_acc = count <= SMALL_PLAN_MAX ? 1 : 0;

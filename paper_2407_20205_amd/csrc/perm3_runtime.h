@@ -104,6 +104,7 @@ struct Launch {
     int32_t small_blocks;         // k_small's grid when the caller knows the work (0: the full grid)
     int32_t zero_acc;             // clear the accumulator words first (a set not known to hold zeros)
     int32_t cls;                  // tuning class (PERM_TUNE_*)
+    int32_t defer;                // the walk re-walks candidate blocks one lane each (batches)
 };
 
 using GraphKey = std::tuple<int, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, uintptr_t, int, int>;

@@ -382,7 +382,7 @@ int32_t Context::enqueue(const Launch &L, const WorkSet &w, const perm_tuning &t
         HIP_TRY(bytes ? launch_pack_u8(pk, st) : launch_pack_planes(pp, st));
     }
     if (timed) HIP_TRY(hipEventRecord(ev_walk0, st));
-    HIP_TRY(launch_walk(walk_args(w, L.count, L.out_dev, L.hist_dev), tn.states_per_lane, grid, st));
+    HIP_TRY(launch_walk(walk_args(w, L.count, L.out_dev, L.hist_dev), tn.states_per_lane, L.defer != 0, grid, st));
     if (timed) {
         HIP_TRY(hipEventRecord(ev_walk1, st));
         HIP_TRY(hipEventRecord(ev_all1, st));
@@ -560,6 +560,7 @@ int32_t Context::run_host(const uint8_t *const *As, const int32_t *ns, int32_t c
     L.range_hi = hi;
     L.fused_only = fused_only ? 1 : 0;
     L.cls = cls;
+    L.defer = count > 1 || ns[0] <= 32 ? 1 : 0;
     // one wave per task (4 per block): blocks beyond the tasks would only start and leave
     if (fused_only) L.small_blocks = (int32_t)std::min<uint64_t>((tasks + 3) / 4, (uint64_t)grid_blocks(tn(cls)));
     rc = run(L, st, false);
@@ -715,6 +716,7 @@ int32_t perm_mod3_batch_dev(const uint8_t *mats_dev, const int64_t *offs_dev, co
     L.out_dev = out_dev;
     L.hist_dev = hist_dev;
     L.cls = count == 1 ? PERM_TUNE_LARGE : PERM_TUNE_BATCH;
+    L.defer = count > 1 ? 1 : 0;
     return run_device_call(L, stream);
 }
 
@@ -736,6 +738,7 @@ int32_t perm_mod3_batch_packed(const uint64_t *planes_dev, const int64_t *row_of
     L.out_dev = out_dev;
     L.hist_dev = hist_dev;
     L.cls = count == 1 ? PERM_TUNE_LARGE : PERM_TUNE_BATCH;
+    L.defer = count > 1 ? 1 : 0;
     return run_device_call(L, stream);
 }
 
@@ -864,6 +867,7 @@ int32_t perm_mod3_census(int32_t n, int32_t generator, uint64_t key, uint64_t fi
             L.out_dev = out;
             L.hist_dev = (uint64_t *)dcounts;
             L.cls = PERM_TUNE_BATCH;
+            L.defer = 1;
             if ((rc = c->enqueue(L, c->ws, c->tn(PERM_TUNE_BATCH), st, false))) return rc;
         }
     }

@@ -32,6 +32,23 @@
 #ifndef PERM3_UNIFORM
 #define PERM3_UNIFORM(x) __builtin_amdgcn_readfirstlane(x)
 #endif
+// Wave-level primitives of the deferred re-walks: a ballot over the active
+// lanes, this lane's index, the number of set bits of a lane mask below this
+// lane, a 32-bit value read from another lane, and the ordering of a wave's
+// LDS accesses (entries one lane writes are read by another).
+#ifndef PERM3_BALLOT
+#define PERM3_BALLOT(p) ((uint64_t)__ballot(p))
+#define PERM3_LANE() ((int)__lane_id())
+#define PERM3_RANK(mask) \
+    ((uint32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)((mask) >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)(mask), 0u)))
+#define PERM3_SHFL32(v, src) ((uint32_t)__shfl((int)(v), (src)))
+#define PERM3_WAVE_LDS_SYNC()                                  \
+    do {                                                       \
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront"); \
+        __builtin_amdgcn_wave_barrier();                       \
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront"); \
+    } while (0)
+#endif
 
 namespace perm3 {
 
@@ -226,6 +243,100 @@ PERM3_FN int rewalk_back(RP R, int n, I ia, I ib, uint32_t ml, uint32_t sl, cons
     return tally;
 }
 
+// Candidate blocks of a wave, re-walked later all together (one lane per
+// block) instead of each by the whole wave at once: an entry holds the lane
+// whose chunk it is (bits 26..31), whether the block ends on a boundary step
+// (bit 25) and the block number (bits 0..24; blocks per chunk are at most
+// 2^(24-4)).  Up to CAND_CAP entries per wave, in LDS; the walk kernels run
+// 4 waves per workgroup.
+constexpr uint32_t CAND_CAP = 128;
+constexpr int CAND_WAVES = 4;
+
+#ifndef PERM3_CAND_LIST
+PERM3_FN uint32_t *cand_list()
+{
+    __shared__ uint32_t lists[CAND_WAVES][CAND_CAP];
+    return lists[threadIdx.x >> 6];
+}
+#define PERM3_CAND_LIST() perm3::cand_list()
+#endif
+
+PERM3_FN uint64_t shfl_from(uint64_t v, int src)
+{
+    const uint32_t lo = PERM3_SHFL32((uint32_t)v, src);
+    const uint32_t hi = PERM3_SHFL32((uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+PERM3_FN u128 shfl_from(u128 v, int src)
+{
+    const uint64_t lo = shfl_from((uint64_t)v, src);
+    const uint64_t hi = shfl_from((uint64_t)(v >> 64), src);
+    return ((u128)hi << 64) | lo;
+}
+
+// The exact terms of one candidate block, walked forward from the Gray state
+// at its first index ia (a multiple of U = 2^UL): indices ia+1 .. ia+U-1 and,
+// when the block closes on a boundary step (inner), ia+U.  Lanes re-walk
+// different blocks side by side, all at the same offset k, so the row flipped
+// at k < U is t = ctz(k) for every lane and comes in by a scalar load; its
+// direction is bit t+1 of k, except at t = UL-1 where it is the parity of the
+// lane's block number.  Only the closing step's row depends on the lane
+// (t = UL + ctz(b+1)).
+template <int UL, typename RP, typename I, typename MK>
+PERM3_FN int rewalk_block(RP R, int n, I ia, uint32_t b, bool inner, uint32_t ml, uint32_t sl, const MK &mk)
+{
+    constexpr uint32_t U = 1u << UL;
+    int tally = 0;
+#pragma nounroll
+    for (uint32_t k = 1; k < U; ++k) {
+        const int t = PERM3_UNIFORM(__builtin_ctz(k));
+        const bool leave = t < UL - 1 ? ((k >> (t + 1)) & 1u) != 0 : (b & 1u) != 0;
+        bip_add(ml, sl, R[t].m_lo, leave ? R[t].sn_lo : R[t].s_lo);
+        tally += exact_term(R, n, ia + (I)k, ml, sl, mk);
+    }
+    if (inner) {
+        const uint32_t jb = b + 1;
+        const int t = UL + __builtin_ctz(jb);
+        const bool leave = ((jb >> (t + 1 - UL)) & 1u) != 0;
+        bip_add(ml, sl, R[t].m_lo, leave ? R[t].sn_lo : R[t].s_lo);
+        tally += exact_term(R, n, ia + (I)U, ml, sl, mk);
+    }
+    return tally;
+}
+
+// The exact terms of the candidate blocks a wave noted, list[0 .. ncand):
+// every active lane takes entries in turn, jumps to the Gray state at its
+// block's first index (Section 3.1) and re-walks the block (rewalk_block).
+// A block then costs one lane instead of the whole wave.
+template <int UL, int S, typename RP, typename I, typename MK>
+PERM3_FN int flush_candidates(RP R, int n, int m, I c, const MK &mk, const uint32_t *list, uint32_t ncand)
+{
+    constexpr uint32_t U = 1u << UL;
+    PERM3_WAVE_LDS_SYNC();
+    const uint64_t act = PERM3_BALLOT(true);
+    const uint32_t nact = (uint32_t)__builtin_popcountll(act);
+    const uint32_t me = PERM3_RANK(act);
+    int tally = 0;
+    for (uint32_t base = 0; base < ncand; base += nact) {
+        const uint32_t j = base + me;
+        const uint32_t e = j < ncand ? list[j] : 0u;
+        const I ce = shfl_from(c, (int)(e >> 26));   // every active lane takes part
+        if (j < ncand) {
+            const uint32_t b = e & 0x1FFFFFFu;
+            const bool inner = ((e >> 25) & 1u) != 0;
+#pragma unroll
+            for (int q = 0; q < S; ++q) {
+                const I ia = ((ce + (I)(64u * q)) << m) + (I)(b * U);
+                uint32_t ml, sl;
+                seed_lo(R, n, ia, ml, sl);
+                tally += rewalk_block<UL>(R, n, ia, b, inner, ml, sl, mk);
+            }
+        }
+    }
+    return tally;
+}
+
 // Fast walk of S whole aligned chunks c + 64 s (s = 0 .. S-1) of length
 // 2^m, m > UL, carried side by side in one lane.
 //
@@ -246,12 +357,14 @@ PERM3_FN int rewalk_back(RP R, int n, I ia, I ib, uint32_t ml, uint32_t sl, cons
 // each low mag word is <= mk.lo, so the block's maximum equals mk.lo exactly
 // when some index in it has all its low columns non-zero (one 3-input max
 // per two states, or per two steps when S = 1).  Only then is the block
-// walked again exactly, backwards from its end state (rewalk_back), so the
-// block keeps no copy of the state it started from.
+// walked again exactly: noted in the wave's candidate list and re-walked by
+// one lane after the chunk (flush_candidates), or, when the list is full,
+// at once by the whole wave, backwards from its end state (rewalk_back), so
+// the block keeps no copy of the state it started from.
 //
 // The chunk index c is a uint64_t for n <= 63 and a u128 for wider matrices
 // (with MasksX); only the seed and the exact terms see its high bits.
-template <int UL, int S, typename RP, typename I, typename MK>
+template <int UL, int S, bool DEFER, typename RP, typename I, typename MK>
 PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const StaticRows<UL> &sr)
 {
     static_assert(S == 1 || S == 2 || S == 4, "1, 2 or 4 states per lane");
@@ -272,6 +385,9 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const Stati
         vs[t] = PERM3_TO_VGPR(sr.s[t]);
         vsn[t] = PERM3_TO_VGPR(sr.sn[t]);
     }
+    uint32_t *const list = DEFER ? PERM3_CAND_LIST() : nullptr;
+    const uint32_t lane_tag = (uint32_t)PERM3_LANE() << 26;
+    uint32_t ncand = 0;
     const uint32_t half = 1u << (m - UL - 1);
     for (uint32_t h = 0; h < 2; ++h) {
         const uint32_t bend = (h + 1) * half;
@@ -311,12 +427,31 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const Stati
                     }
                 }
             }
-            if (acc == mk.lo) {
-                const uint32_t last = b * U + U - (inner ? 0u : 1u);
+            const bool cand = acc == mk.lo;
+            if (!DEFER) {
+                if (cand) {
+                    const uint32_t last = b * U + U - (inner ? 0u : 1u);
 #pragma unroll
-                for (int q = 0; q < S; ++q) {
-                    const I i0 = (c + (I)(64u * q)) << m;
-                    tally += rewalk_back(R, n, i0 + b * U, i0 + last, ml[q], sl[q], mk);
+                    for (int q = 0; q < S; ++q) {
+                        const I i0 = (c + (I)(64u * q)) << m;
+                        tally += rewalk_back(R, n, i0 + b * U, i0 + last, ml[q], sl[q], mk);
+                    }
+                }
+                continue;
+            }
+            const uint64_t cands = PERM3_BALLOT(cand);
+            if (cands) {
+                const uint32_t nc = (uint32_t)__builtin_popcountll(cands);
+                if (ncand + nc <= CAND_CAP) {
+                    if (cand) list[ncand + PERM3_RANK(cands)] = lane_tag | (inner ? 1u << 25 : 0u) | b;
+                    ncand += nc;
+                } else if (cand) {
+                    const uint32_t last = b * U + U - (inner ? 0u : 1u);
+#pragma unroll
+                    for (int q = 0; q < S; ++q) {
+                        const I i0 = (c + (I)(64u * q)) << m;
+                        tally += rewalk_back(R, n, i0 + b * U, i0 + last, ml[q], sl[q], mk);
+                    }
                 }
             }
         }
@@ -331,6 +466,7 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const Stati
             }
         }
     }
+    if (DEFER && ncand) tally += flush_candidates<UL, S>(R, n, m, c, mk, list, ncand);
     return tally;
 }
 
@@ -353,7 +489,7 @@ PERM3_FN MasksX masks_wide(int n)
 // 2^128.  A whole chunk of a fast-mode matrix takes the unrolled walk; a
 // ragged end (or a small matrix) is seeded at its first index and tests every
 // index on the low word, forming the other words only where it passes.
-template <int UL, typename RP>
+template <int UL, bool DEFER, typename RP>
 PERM3_FN int walk_lane_wide(RP R, int n, int m, bool fast, u128 c0, uint64_t off_lo, uint64_t off_hi,
                             uint64_t cr, const MasksX &mk, const StaticRows<UL> &sr)
 {
@@ -362,7 +498,7 @@ PERM3_FN int walk_lane_wide(RP R, int n, int m, bool fast, u128 c0, uint64_t off
     const uint64_t oa = oa0 > off_lo ? oa0 : off_lo;
     const uint64_t oe = oe0 < off_hi ? oe0 : off_hi;
     if (oa >= oe) return 0;
-    if (fast && oa == oa0 && oe == oe0) return walk_chunks_fast<UL, 1>(R, n, m, c0 + cr, mk, sr);
+    if (fast && oa == oa0 && oe == oe0) return walk_chunks_fast<UL, 1, DEFER>(R, n, m, c0 + cr, mk, sr);
     const u128 base = c0 << m;
     const u128 ia = base + oa;
     uint32_t ml, sl;

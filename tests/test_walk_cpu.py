@@ -162,6 +162,23 @@ def test_fast_walk_chunks_vs_oracle(harness):
         assert int(line) == sum(oracle.range_tally(A, a, b) for A, a, b in parts), parts[0][1:]
 
 
+def test_candidate_list_and_its_overflow_vs_oracle(harness):
+    """Blocks holding a candidate are noted (up to 128 per wave) and re-walked after the chunk; past
+    that the rest are re-walked at once.  A hit-heavy matrix makes nearly every block a candidate:
+    2^(m - UL) blocks below, at and far above the list's size, for every block length."""
+    cases, want = [], []
+    for ul in (4, 5, 6):
+        for blocks_log in (1, 6, 7, 8, 10):
+            m = ul + blocks_log
+            n = m + 8
+            for k, A in enumerate((hit_heavy(n, 900 + ul * 10 + blocks_log), W.uniform_matrix(n, 950 + ul))):
+                c = 3 + k
+                cases.append(f"chunks {ul} 1 {n} {m} {c} {digits(A)}")
+                want.append((A, c << m, (c + 1) << m))
+    for line, (A, a, b) in zip(harness(cases), want):
+        assert int(line) == oracle.range_tally(A, a, b), (A.shape[0], a, b)
+
+
 def test_direct_chunks_and_ranges_vs_oracle(harness):
     g = W.rng(10)
     cases, want = [], []

@@ -46,6 +46,16 @@ static inline uint32_t cpu_bitop3(uint32_t a, uint32_t b, uint32_t c, uint32_t t
 #define PERM3_BITOP3(a, b, c, tt) cpu_bitop3((a), (b), (c), (tt))
 #define PERM3_UNIFORM(x) (x)
 #define PERM3_TO_VGPR(x) (x)
+// a wave of one lane
+#define PERM3_BALLOT(p) ((uint64_t)((p) ? 1u : 0u))
+#define PERM3_LANE() 0
+#define PERM3_RANK(mask) 0u
+#define PERM3_SHFL32(v, src) ((uint32_t)(v))
+#define PERM3_WAVE_LDS_SYNC() \
+    do {                      \
+    } while (0)
+static uint32_t g_cand_list[128];
+#define PERM3_CAND_LIST() g_cand_list
 
 #include "perm3_plan.hpp"
 #include "perm3_walk.hpp"
@@ -132,7 +142,14 @@ static long long chunks_ul_s(const RowW *R, int n, int m, uint64_t c)
 {
     StaticRows<UL> sr;
     load_static_rows<UL>(R, sr);
-    return walk_chunks_fast<UL, S>(R, n, m, c, masks_of(n), sr);
+    // both ways of re-walking candidate blocks: noted and re-walked after the chunk, or at once
+    const long long deferred = walk_chunks_fast<UL, S, true>(R, n, m, c, masks_of(n), sr);
+    const long long direct = walk_chunks_fast<UL, S, false>(R, n, m, c, masks_of(n), sr);
+    if (deferred != direct) {
+        printf("error\n");
+        exit(1);
+    }
+    return deferred;
 }
 
 static long long chunks(int ul, int s, const RowW *R, int n, int m, uint64_t c)
@@ -157,7 +174,13 @@ static long long wide_ul(const RowX *R, int n, int m, bool fast, u128 c0, uint64
 {
     StaticRows<UL> sr;
     load_static_rows<UL>(R, sr);
-    return walk_lane_wide<UL>(R, n, m, fast, c0, off_lo, off_hi, cr, masks_wide(n), sr);
+    const long long deferred = walk_lane_wide<UL, true>(R, n, m, fast, c0, off_lo, off_hi, cr, masks_wide(n), sr);
+    const long long direct = walk_lane_wide<UL, false>(R, n, m, fast, c0, off_lo, off_hi, cr, masks_wide(n), sr);
+    if (deferred != direct) {
+        printf("error\n");
+        exit(1);
+    }
+    return deferred;
 }
 
 int main()
