@@ -70,6 +70,35 @@ def measured_traffic():
     return d["traffic_bytes_per_launch"] if d else None
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+GOLDEN_MISMATCH = []   # names of workloads whose results differ from the oracle's stored ones
+
+
+def read_golden(name):
+    """A stored expected-value file (written by tests/golden/make_full_goldens.py from the CPU oracle
+    alone): 'key value' lines, the repeated 'results' and 'hist' keys collected in lists."""
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as f:
+        for line in f:
+            line = line.strip()
+            if not line or line.startswith("#"):
+                continue
+            key, _, val = line.partition(" ")
+            if key in ("results", "hist"):
+                out.setdefault(key, []).append(val)
+            else:
+                out[key] = val
+    return out
+
+
+def check_golden(name, same, detail):
+    """Record whether a workload's results equal the oracle's stored ones."""
+    if not same:
+        GOLDEN_MISMATCH.append(name)
+        log(f"ERROR: {name} differs from the oracle's expected values in tests/golden/")
+    return {"file": "tests/golden/" + name, "match": bool(same), **detail}
+
+
 def tuning_info(P, cls):
     """Which tuning a class of call runs with: its source (default, cache, set, autotune) and values."""
     t, src = P.tuning_get_class(cls)
@@ -111,6 +140,10 @@ def bench_headline(P, W, torch, steps, warmup):
     t1 = time.perf_counter()
     P.timing_enable(False)
     result = int(out.item())
+    g = read_golden("full_single36.txt")
+    golden = check_golden("full_single36.txt",
+                          g["input_sha256"] == W.sha256(A) and result == int(g["perm_mod3"]),
+                          {"oracle_tally": int(g["tally"]), "oracle_perm_mod3": int(g["perm_mod3"])})
     sec = t1 - t0
     hot_s = float(np.mean(hot)) * 1e-3
     achieved = OPS_PER_TERM * terms / hot_s
@@ -123,6 +156,7 @@ def bench_headline(P, W, torch, steps, warmup):
         "input_sha256": input_sha256(A),
         "launches_ms_mean": float(np.mean(total)),
         "result": result,
+        "oracle_golden": golden,
         "roofline": {
             "bound": "alu",
             "achieved": achieved / 1e12,
@@ -190,6 +224,13 @@ def bench_batch(P, W, torch, reps, baseline=True):
     res = out.cpu().numpy()
     h = hist.cpu().numpy().reshape(64, 3) // reps
     per_n = {int(n): [int(x) for x in h[n]] for n in range(12, 29)}
+    g = read_golden("full_batch8192.txt")
+    want = np.array([int(ch) for ch in "".join(g["results"])], np.uint8)
+    want_hist = {int(row.split()[0]): [int(x) for x in row.split()[1:]] for row in g["hist"]}
+    bad = int(np.count_nonzero(res != want)) if want.size == res.size else -1
+    golden = check_golden("full_batch8192.txt",
+                          g["input_sha256"] == W.sha256(b.ns, *b.mats) and bad == 0 and per_n == want_hist,
+                          {"results_differing": bad, "hist_equal": per_n == want_hist})
 
     result = {
         "workload": "8192 matrices, n uniform on 12..28, uniform entries, packed (mag, sgn) uint64 planes",
@@ -199,6 +240,7 @@ def bench_batch(P, W, torch, reps, baseline=True):
         "hist_per_n": per_n,
         "zero_fraction": float(np.mean(res == 0)),
         "input_sha256": input_sha256(*b.mats),
+        "oracle_golden": golden,
     }
     if not baseline:
         return result
@@ -601,6 +643,17 @@ def bench_serve(P, W, torch, rate, count, batched_terms_per_s, quantum=1 << 33, 
     log(f"serve: budget 2^36 done in {qspan:.2f} s, p50 {pct(qlat, 50):.3f} ms, p99 {pct(qlat, 99):.3f} ms")
     blat, bres, bspan = replay_fifo_baseline(P, tr)
     log(f"serve: FIFO baseline done in {bspan:.2f} s")
+    g = read_golden("full_serve_le28.txt")
+    if int(g["count"]) == count:
+        want = "".join(g["results"])
+        checked = [k for k in range(count) if want[k] != "-"]
+        bad = sum(1 for k in checked if res[k] != int(want[k]))
+        golden = check_golden("full_serve_le28.txt",
+                              g["input_sha256"] == W.sha256(tr.ns, *tr.mats) and bad == 0 and len(checked) > 0,
+                              {"checked": len(checked), "results_differing": bad})
+    else:
+        golden = {"file": "tests/golden/full_serve_le28.txt", "match": None,
+                  "skipped": f"the stored values are for the {g['count']}-request trace, this one has {count}"}
     return {
         "workload": f"{count} requests, n in 8..40 with P(n) ~ 1.15^-(n-8), Poisson arrivals at {rate:.1f}/s "
                     "(0.7 x batched capacity / E[2^n]), uniform entries",
@@ -614,6 +667,7 @@ def bench_serve(P, W, torch, rate, count, batched_terms_per_s, quantum=1 << 33, 
         "baseline_fifo_one_launch_per_request": {"p50_ms": pct(blat, 50), "p99_ms": pct(blat, 99),
                                                  "requests_per_s": count / bspan},
         "results_identical_to_baseline": bool(res == bres),
+        "oracle_golden": golden,
         "work_budget": 1 << 44,
         "budgeted_2pow36": {"work_budget": budget, "requests_per_s": count / qspan, "p50_ms": pct(qlat, 50),
                             "p99_ms": pct(qlat, 99), "mean_ms": float(np.mean(qlat)), "ticks": int(qst.ticks),
@@ -779,7 +833,11 @@ def main():
     if args.only is None and not args.no_cpu:
         line["cpu_baseline"] = bench_cpu(W)
         log(f"cpu oracle: {line['cpu_baseline']['value']:.3e} terms/s on {line['cpu_baseline']['cores']} threads")
+    if GOLDEN_MISMATCH:
+        line["oracle_golden_mismatch"] = GOLDEN_MISMATCH
     print(json.dumps(line), flush=True)
+    if GOLDEN_MISMATCH:
+        sys.exit(3)
 
 
 if __name__ == "__main__":
