@@ -232,10 +232,15 @@ def bench_batch(P, W, torch, reps, baseline=True):
                           g["input_sha256"] == W.sha256(b.ns, *b.mats) and bad == 0 and per_n == want_hist,
                           {"results_differing": bad, "hist_equal": per_n == want_hist})
 
+    achieved = OPS_PER_TERM * terms / sec
     result = {
         "workload": "8192 matrices, n uniform on 12..28, uniform entries, packed (mag, sgn) uint64 planes",
         "matrices_per_s": b.count / sec,
         "terms_per_s": terms / sec,
+        # the whole call per batch (plan, pack, walk) by the host clock over graph replays
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
+                     "unit": "T int32 lane-ops/s", "frac": achieved / PEAK_LANE_OPS, "ops_per_term": OPS_PER_TERM,
+                     "kernel": "k_walk<1, true> (candidate blocks re-walked one lane each)"},
         "ms_per_batch": 1e3 * sec,
         "hist_per_n": per_n,
         "zero_fraction": float(np.mean(res == 0)),
