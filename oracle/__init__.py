@@ -8,7 +8,9 @@ Two independent definitions live here:
 
 * ``brute_perm`` -- the permanent by its definition, eq. (1): a sum over all
   n! permutations of products of entries, in exact Python integers.  Used for
-  n <= 8.
+  n <= 8.  ``perm_mod3_stack`` is the same sum mod 3 with the permutations
+  grouped by the columns of the first rows, vectorised over stacks of up to
+  millions of matrices of one order n <= 12.
 * the C oracle (``perm3_oracle.c``) -- Ryser's identity, eq. (2), walked in
   reflected-binary Gray-code order with UNPACKED centred residues (Section 3
   with its cmod3 reduction), threaded over blocks of consecutive Gray indices
@@ -262,3 +264,39 @@ def brute_perm(A) -> int:
 
 def brute_perm_mod3(A) -> int:
     return brute_perm(A) % 3
+
+
+def perm_mod3_stack(mats) -> np.ndarray:
+    """perm mod 3 in {0, 1, 2} of every matrix of a stack of shape (m, n, n), n <= 12, by eq. (1)
+    with its sum over permutations grouped by the set of columns that the first rows take.
+
+    For a column set S let f(S) be the sum, over the bijections sigma from rows 0 .. |S|-1 onto S,
+    of prod_i a_{i, sigma(i)}.  Then f(empty set) = 1 (the empty product), and splitting on the
+    column j = sigma(|S| - 1) of the last of those rows gives
+        f(S) = sum over j in S of a_{|S|-1, j} * f(S minus {j}),
+    so perm(A) = f(all n columns).  Residues stay in {0, 1, 2} (2 is -1) and every step reduces
+    mod 3.  Vectorised over the stack in chunks, so millions of small matrices take seconds."""
+    M = np.asarray(mats, dtype=np.uint8)
+    if M.ndim != 3 or M.shape[1] != M.shape[2]:
+        raise ValueError("stack of square matrices expected")
+    m, n = M.shape[0], M.shape[1]
+    if n > 12:
+        raise ValueError("n must be at most 12")
+    if np.any(M > 2):
+        raise ValueError("entries must be in {0, 1, 2}")
+    out = np.empty(m, dtype=np.uint8)
+    chunk = max(1, (1 << 24) >> n)
+    for c0 in range(0, m, chunk):
+        # column-major copy: A[row, j] is one contiguous vector over the chunk
+        A = np.ascontiguousarray(M[c0:c0 + chunk].transpose(1, 2, 0))
+        f = np.zeros((1 << n, A.shape[2]), dtype=np.uint8)
+        f[0] = 1
+        for S in range(1, 1 << n):
+            row = bin(S).count("1") - 1
+            acc = np.zeros(A.shape[2], dtype=np.uint8)     # at most 4 n <= 48: no overflow
+            for j in range(n):
+                if S >> j & 1:
+                    acc += A[row, j] * f[S & ~(1 << j)]
+            f[S] = acc % 3
+        out[c0:c0 + chunk] = f[(1 << n) - 1]
+    return out

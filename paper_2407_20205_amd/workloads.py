@@ -113,6 +113,18 @@ def batch_uniform(count: int = 8192, n_lo: int = 12, n_hi: int = 28,
     return Batch(ns=ns, mats=mats, seed=seed)
 
 
+def batch_flat(count: int, n_lo: int, n_hi: int, seed: int) -> tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """``count`` matrices, n uniform on [n_lo, n_hi], entries uniform, drawn straight into one
+    buffer (for batches of millions of matrices): returns (ns int32[count], offs int64[count + 1]
+    byte offsets, buf uint8[offs[-1]]), matrix k row-major at buf[offs[k]:offs[k + 1]]."""
+    g = rng(seed)
+    ns = g.integers(n_lo, n_hi + 1, size=count).astype(np.int32)
+    offs = np.zeros(count + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(ns.astype(np.int64) ** 2)
+    buf = g.integers(0, 3, size=int(offs[-1]), dtype=np.uint8)
+    return ns, offs, buf
+
+
 def large_sparse(seed: int = SEED_LARGE, n_big: int = 44, n_sparse: int = 40,
                  count_sparse: int = 64) -> tuple[np.ndarray, Batch]:
     """One n_big x n_big uniform matrix plus ``count_sparse`` n_sparse matrices with P(0) = 0.6."""

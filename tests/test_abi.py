@@ -126,6 +126,18 @@ def test_argument_errors_need_no_device():
     assert L.perm_mod3(None, 3, None) == P.PERM_EINVAL
     assert L.perm_mod3_batch_dev(None, None, None, -1, None, None, None) == P.PERM_EINVAL
     assert L.perm_mod3_batch_dev(None, None, None, 0, None, None, None) == P.PERM_OK
+    # counts: 0 is an empty call, PERM_MAX_BATCH + 1 (the allocation-free call: its own limit + 1)
+    # is refused before any pointer is looked at
+    over = P.PERM_MAX_BATCH + 1
+    for fn in (L.perm_mod3_batch_dev, L.perm_mod3_batch_packed):
+        assert fn(None, None, None, over, None, None, None) == P.PERM_EINVAL
+        assert fn(None, None, None, 0, None, None, None) == P.PERM_OK
+    assert L.perm_mod3_batch_packed_noalloc(None, None, None, P.PERM_NOALLOC_MAX_COUNT + 1, None, None,
+                                            None) == P.PERM_EINVAL
+    assert L.perm_mod3_batch_packed_noalloc(None, None, None, 0, None, None, None) == P.PERM_OK
+    assert L.perm_mod3_batch(None, None, over, None) == P.PERM_EINVAL
+    assert L.perm_mod3_batch(None, None, 0, None) == P.PERM_OK
+    assert P.perm_mod3_batch([]).shape == (0,)
 
 
 def test_compute_without_gpu_fails_loudly():

@@ -143,3 +143,30 @@ def test_monte_carlo_batch_workload_sampled():
     # the same matrices alone give the same answers as in the batch
     for k in big[:6]:
         assert P.perm_mod3(b.mats[k]) == got[k]
+
+
+def test_batch_at_the_count_limit_every_result():
+    """PERM_MAX_BATCH = 2^22 matrices, n uniform on 0..8, bytes in device memory, one call with a
+    histogram: every result against the oracle's stacked permanent, order by order."""
+    import torch
+    count = P.PERM_MAX_BATCH
+    ns, offs, buf = W.batch_flat(count, 0, 8, seed=36)
+    flush_print(f"{count} matrices, {buf.size} bytes")
+    out = torch.full((count,), 0xEE, dtype=torch.uint8, device="cuda")
+    hist = torch.zeros(64 * 3, dtype=torch.int64, device="cuda")
+    P.perm_mod3_batch_dev(to_dev(buf, torch.uint8), to_dev(offs[:-1], torch.int64), to_dev(ns, torch.int32), out,
+                          hist, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    want = np.empty(count, np.uint8)
+    for n in range(0, 9):
+        idx = np.nonzero(ns == n)[0]
+        # matrices of one order sit at offsets offs[idx]: gather their n*n bytes as a stack
+        gather = offs[idx][:, None] + np.arange(n * n, dtype=np.int64)[None, :]
+        want[idx] = oracle.perm_mod3_stack(buf[gather].reshape(idx.size, n, n))
+    bad = np.nonzero(got != want)[0]
+    assert bad.size == 0, (bad[:8].tolist(), ns[bad[:8]].tolist())
+    h = hist.cpu().numpy().reshape(64, 3)
+    for n in range(0, 9):
+        assert h[n].tolist() == np.bincount(want[ns == n], minlength=3).tolist(), n
+    assert int(h.sum()) == count
