@@ -11,13 +11,17 @@
 //
 // k_census_lanes: one matrix at a time per lane for n <= CENSUS_LANE_MAX_N,
 // each lane over a run of consecutive matrices.  The lane walks all 2^n - 1
-// Gray steps of its matrix with every index tested (the
-// rows sit in LDS, one column of words per lane; all lanes flip the same row
-// at the same step), forms ((-1)^n T) mod 3, and the wave counts results 0,
-// 1 and 2 with ballots.  Larger n: k_generate writes the matrices and the
-// batch walk takes them.
+// Gray steps of its matrix (the rows sit in LDS, one column of words per lane;
+// all lanes flip the same row at the same step), with every index tested for
+// small n (k_census_lanes) and, from CENSUS_FILTER_MIN_N on, a block of 16
+// indices tested at once and re-walked exactly only when it holds a candidate
+// (k_census_filtered); it forms ((-1)^n T) mod 3, and the wave counts results
+// 0, 1 and 2 with ballots.
+// Larger n: k_generate writes the matrices and the batch walk takes them.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <algorithm>
 
 #include "perm3_internal.h"
 #include "perm3_walk.hpp"
@@ -104,15 +108,22 @@ __device__ int census_walk_blocks(int n, uint32_t mask, int tid, const uint32_t 
     const uint32_t nblocks = 1u << (n - CENSUS_UL);
     uint32_t ml = 0, sl = 0;
     int tally = 0;
+    // the row closing block b is read one block ahead (rows 4 .. n-1 exist: n > 4)
+    uint32_t next_m = CROW(s_m, CENSUS_UL), next_s = CROW(s_s, CENSUS_UL);
     for (uint32_t b = 0; b < nblocks; ++b) {
         // the step closing block b enters index 16 (b + 1); the last block has none
         const uint32_t jb = b + 1;
         const bool closing = jb < nblocks;
-        const int tb = closing ? CENSUS_UL + __builtin_ctz(jb) : 0;   // a row of the matrix either way
-        const int sh = closing ? tb - CENSUS_UL + 1 : 0;
+        const int tb = closing ? CENSUS_UL + __builtin_ctz(jb) : CENSUS_UL;
+        const int sh = tb - CENSUS_UL + 1;
         const bool leave_b = closing && ((jb >> sh) & 1u);
-        const uint32_t bm = closing ? CROW(s_m, tb) : 0u;
-        const uint32_t bs0 = closing ? CROW(s_s, tb) : 0u;
+        const uint32_t bm = closing ? next_m : 0u;
+        const uint32_t bs0 = closing ? next_s : 0u;
+        if (jb + 1 < nblocks) {
+            const int tn = CENSUS_UL + __builtin_ctz(jb + 1);
+            next_m = CROW(s_m, tn);
+            next_s = CROW(s_s, tn);
+        }
         const uint32_t bs = leave_b ? (bs0 ^ bm) : bs0;
 #pragma unroll
         for (int k = 1; k <= U; ++k) {
@@ -136,6 +147,229 @@ __device__ int census_walk_blocks(int n, uint32_t mask, int tid, const uint32_t 
         }
     }
     return tally;
+}
+
+// From this n on (SplitMix64 matrices) the lanes test a block's 16 indices at
+// once and re-walk only the blocks that hold a candidate.  Below it an index is
+// a candidate so often ((2/3)^n) that the re-walks cost more than testing
+// every index (n = 8 breaks even, n = 7 loses 6%, n = 9 gains 11%).
+constexpr int CENSUS_FILTER_MIN_N = 9;
+// A wave's list of candidate blocks: re-walked 64 at a time, one per lane.
+constexpr int CENSUS_CAND_CAP = 128;
+
+struct CensusCand {
+    uint32_t ml, sl;   // the Gray state at the block's first index, 16 b
+    uint32_t tag;      // the lane whose matrix it is, from bit 26; the block b below
+};
+
+// The filtered lanes keep rows 0..3 of their matrix in registers (another
+// lane's come by a shuffle) and rows 4..n-1 in LDS: row i of lane tid at
+// [(i - 4) * CENSUS_BLOCK + tid].
+#define FROW(a, i, who) (a)[((i) - CENSUS_UL) * CENSUS_BLOCK + (who)]
+
+// The exact walk of entries list[0 .. cnt) (cnt <= 64), lane j taking entry j:
+// the 16 indices after 16 b from the saved state, with the rows of the lane
+// the block belongs to (rows 0..3 from that lane's registers, the closing row
+// from LDS), every index tested.  Each entry's tally is added to that lane's
+// word in s_tally.  Every lane of the wave calls it.
+__device__ __forceinline__ void census_flush(uint32_t mask, uint32_t nblocks, int wave_base, int lane,
+                                             const uint32_t (&r_m)[CENSUS_UL], const uint32_t (&r_s)[CENSUS_UL],
+                                             const uint32_t *s_m, const uint32_t *s_s, const CensusCand *list,
+                                             uint32_t cnt, int *s_tally)
+{
+    PERM3_WAVE_LDS_SYNC();
+    // entries at and above cnt are stale but inside the list: read, never used
+    const CensusCand e = list[lane];
+    const int src_lane = (int)(e.tag >> 26);
+    uint32_t vm[CENSUS_UL], vs[CENSUS_UL], vsn[CENSUS_UL];
+#pragma unroll
+    for (int t = 0; t < CENSUS_UL; ++t) {
+        vm[t] = PERM3_SHFL32(r_m[t], src_lane);
+        vs[t] = PERM3_SHFL32(r_s[t], src_lane);
+        vsn[t] = vs[t] ^ vm[t];
+    }
+    if ((uint32_t)lane < cnt) {
+        const int src = wave_base + src_lane;
+        const uint32_t b = e.tag & ((1u << 26) - 1u);
+        const uint32_t jb = b + 1;
+        const bool closing = jb < nblocks;
+        const int tb = closing ? CENSUS_UL + __builtin_ctz(jb) : CENSUS_UL;
+        const bool leave_b = closing && ((jb >> (tb - CENSUS_UL + 1)) & 1u);
+        const uint32_t bm = closing ? FROW(s_m, tb, src) : 0u;
+        const uint32_t bs0 = closing ? FROW(s_s, tb, src) : 0u;
+        const uint32_t bs = leave_b ? (bs0 ^ bm) : bs0;
+        uint32_t ml = e.ml, sl = e.sl;
+        int part = 0;
+#pragma unroll
+        for (int k = 1; k <= (1 << CENSUS_UL); ++k) {
+            uint32_t rm, rs;
+            if (k < (1 << CENSUS_UL)) {
+                const int t = __builtin_ctz(k);
+                rm = vm[t];
+                const bool leave = t + 1 < CENSUS_UL ? ((k >> (t + 1)) & 1) != 0 : (b & 1u) != 0;
+                rs = leave ? vsn[t] : vs[t];
+            } else {
+                rm = bm;
+                rs = bs;
+            }
+            bip_add(ml, sl, rm, rs);
+            // the index 16 b + k has the parity of k
+            const int odd = (__builtin_popcount(sl) + k) & 1;
+            const bool exists = k < (1 << CENSUS_UL) || closing;
+            part += exists && ml == mask ? (odd ? -1 : 1) : 0;
+        }
+        if (part) atomicAdd(&s_tally[src], part);
+    }
+    PERM3_WAVE_LDS_SYNC();
+}
+
+// The Ryser tally of the lane's matrix for CENSUS_FILTER_MIN_N <= n, found by
+// a filter: the rows have no bit at or above n, so every mag word is at most
+// the mask of n columns and a block of 16 indices holds a non-zero term only
+// if its largest mag word equals the mask.  Such a block is noted (its first
+// Gray state and number) in the wave's list; once 64 are noted, the wave
+// re-walks them exactly, one per lane, whichever lane's matrix each belongs
+// to.  The lane's tally is left in s_tally[tid] once the wave is through.
+__device__ __forceinline__ void census_walk_filtered(int n, uint32_t mask, int tid, bool active,
+                                                     const uint32_t (&r_m)[CENSUS_UL],
+                                                     const uint32_t (&r_s)[CENSUS_UL], const uint32_t *s_m,
+                                                     const uint32_t *s_s, CensusCand *list, int *s_tally)
+{
+    constexpr int U = 1 << CENSUS_UL;
+    const int lane = tid & 63;
+    const int wave_base = tid & ~63;
+    uint32_t vsn[CENSUS_UL];
+#pragma unroll
+    for (int t = 0; t < CENSUS_UL; ++t) vsn[t] = r_s[t] ^ r_m[t];
+    s_tally[tid] = 0;
+    const uint32_t nblocks = 1u << (n - CENSUS_UL);
+    uint32_t ml = 0, sl = 0;
+    uint32_t ncand = 0;
+    // the row closing a block is read from LDS one block ahead
+    uint32_t next_m = FROW(s_m, CENSUS_UL, tid), next_s = FROW(s_s, CENSUS_UL, tid);
+    for (uint32_t b = 0; b < nblocks; ++b) {
+        // the step closing block b enters index 16 (b + 1); the last block has none
+        const uint32_t jb = b + 1;
+        const bool closing = jb < nblocks;
+        const int tb = closing ? CENSUS_UL + __builtin_ctz(jb) : CENSUS_UL;
+        const bool leave_b = closing && ((jb >> (tb - CENSUS_UL + 1)) & 1u);
+        const uint32_t bm = closing ? next_m : 0u;
+        const uint32_t bs0 = closing ? next_s : 0u;
+        if (jb + 1 < nblocks) {
+            const int tn = CENSUS_UL + __builtin_ctz(jb + 1);
+            next_m = FROW(s_m, tn, tid);
+            next_s = FROW(s_s, tn, tid);
+        }
+        const uint32_t bs = leave_b ? (bs0 ^ bm) : bs0;
+        const uint32_t m0 = ml, s0 = sl;
+        uint32_t acc = 0;
+#pragma unroll
+        for (int k = 1; k <= U; ++k) {
+            uint32_t rm, rs;
+            if (k < U) {
+                const int t = __builtin_ctz(k);
+                rm = r_m[t];
+                const bool leave = t + 1 < CENSUS_UL ? ((k >> (t + 1)) & 1) != 0 : (b & 1u) != 0;
+                rs = leave ? vsn[t] : r_s[t];
+            } else {
+                rm = bm;    // the last block adds a zero row: its state stays put
+                rs = bs;
+            }
+            bip_add(ml, sl, rm, rs);
+            acc = acc > ml ? acc : ml;
+        }
+        const bool cand = active && acc == mask;
+        const uint64_t cands = PERM3_BALLOT(cand);
+        if (cands) {
+            if (cand) {
+                CensusCand e;
+                e.ml = m0;
+                e.sl = s0;
+                e.tag = ((uint32_t)lane << 26) | b;
+                list[ncand + PERM3_RANK(cands)] = e;
+            }
+            ncand += (uint32_t)__builtin_popcountll(cands);
+            if (ncand >= 64) {
+                ncand -= 64;
+                census_flush(mask, nblocks, wave_base, lane, r_m, r_s, s_m, s_s, list + ncand, 64, s_tally);
+            }
+        }
+    }
+    if (ncand) census_flush(mask, nblocks, wave_base, lane, r_m, r_s, s_m, s_s, list, ncand, s_tally);
+}
+
+// One row of a SplitMix64 matrix, packed by phi (element j at bit n-1-j),
+// continuing the generator's state x.
+__device__ __forceinline__ void splitmix_row(int n, uint64_t &x, uint32_t &mag, uint32_t &sgn)
+{
+    mag = 0;
+    sgn = 0;
+    for (int j = 0; j < n; ++j) {
+        const uint32_t v = trit_of(splitmix_mix(x));
+        x += SPLITMIX_GAMMA;
+        const uint32_t bit = 1u << (n - 1 - j);
+        mag |= v != 0 ? bit : 0u;
+        sgn |= v == 2 ? bit : 0u;
+    }
+}
+
+// k_census_lanes for SplitMix64 matrices with CENSUS_FILTER_MIN_N <= n <=
+// CENSUS_LANE_MAX_N, through the filtered walk.
+__global__ void __launch_bounds__(CENSUS_BLOCK) k_census_filtered(CensusArgs a)
+{
+    extern __shared__ uint32_t s_rows[];
+    __shared__ CensusCand s_cand[CENSUS_BLOCK / 64][CENSUS_CAND_CAP];
+    __shared__ int s_tally[CENSUS_BLOCK];
+    const int n = a.n;
+    const int nr = n - CENSUS_UL;
+    uint32_t *s_m = s_rows, *s_s = s_rows + nr * CENSUS_BLOCK;
+    const int nn = n * n;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const uint64_t lanes = (uint64_t)gridDim.x * CENSUS_BLOCK;
+    const uint64_t per = (a.count + lanes - 1) / lanes;
+    const uint64_t begin = ((uint64_t)blockIdx.x * CENSUS_BLOCK + tid) * per;
+    const uint32_t mask = (1u << n) - 1u;
+    unsigned long long c0 = 0, c1 = 0, c2 = 0;
+    uint32_t r_m[CENSUS_UL] = {0, 0, 0, 0}, r_s[CENSUS_UL] = {0, 0, 0, 0};
+    uint64_t x = 0;
+    for (uint64_t r = 0; r < per; ++r) {
+        const uint64_t idx = begin + r;
+        const bool active = idx < a.count;
+        if (active) {
+            // matrix t's entries are outputs t n^2 + 1 .. (t+1) n^2: a lane's
+            // run of consecutive matrices continues one stream
+            if (r == 0) x = a.key + ((a.first + idx) * (uint64_t)nn + 1u) * SPLITMIX_GAMMA;
+#pragma unroll
+            for (int i = 0; i < CENSUS_UL; ++i) splitmix_row(n, x, r_m[i], r_s[i]);
+            for (int i = CENSUS_UL; i < n; ++i) {
+                uint32_t mag, sgn;
+                splitmix_row(n, x, mag, sgn);
+                FROW(s_m, i, tid) = mag;
+                FROW(s_s, i, tid) = sgn;
+            }
+        }
+        census_walk_filtered(n, mask, tid, active, r_m, r_s, s_m, s_s, s_cand[tid >> 6], s_tally);
+        const int tally = s_tally[tid];
+        const int p = (n & 1) ? -tally : tally;
+        int res = p % 3;
+        if (res < 0) res += 3;
+        const unsigned long long b0 = __ballot(active && res == 0);
+        const unsigned long long b1 = __ballot(active && res == 1);
+        const unsigned long long b2 = __ballot(active && res == 2);
+        if (lane == 0) {
+            c0 += __popcll(b0);
+            c1 += __popcll(b1);
+            c2 += __popcll(b2);
+        }
+        // every lane's reads of this matrix's rows are done before it writes the next
+        PERM3_WAVE_LDS_SYNC();
+    }
+    if (lane == 0) {
+        if (c0) atomicAdd(&a.counts[0], c0);
+        if (c1) atomicAdd(&a.counts[1], c1);
+        if (c2) atomicAdd(&a.counts[2], c2);
+    }
 }
 
 __global__ void __launch_bounds__(CENSUS_BLOCK) k_census_lanes(CensusArgs a)
@@ -240,11 +474,25 @@ __global__ void __launch_bounds__(256) k_generate(GenArgs a)
     a.ns[idx] = n;
 }
 
-hipError_t launch_census_lanes(const CensusArgs &a, int grid_blocks, hipStream_t st)
+hipError_t launch_census_lanes(const CensusArgs &a, int cus, hipStream_t st)
 {
     if (a.n < 1 || a.n > CENSUS_LANE_MAX_N) return hipErrorInvalidValue;
-    const size_t lds = 2u * (size_t)a.n * CENSUS_BLOCK * sizeof(uint32_t);   // at most 40 KiB
-    hipLaunchKernelGGL(k_census_lanes, dim3(grid_blocks), dim3(CENSUS_BLOCK), lds, st, a);
+    const bool filtered = a.gen == GEN_SPLITMIX && a.n >= CENSUS_FILTER_MIN_N;
+    const int rows = filtered ? a.n - CENSUS_UL : a.n;
+    const size_t lds = 2u * (size_t)rows * CENSUS_BLOCK * sizeof(uint32_t);   // at most 32 KiB
+    // every lane takes an equal run of matrices, so the grid is what stays
+    // resident at once (LDS bounds it for large n)
+    int per_cu = 0;
+    hipError_t e = filtered ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census_filtered, CENSUS_BLOCK, lds)
+                            : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_census_lanes, CENSUS_BLOCK, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) per_cu = 1;
+    const uint64_t want = (a.count + CENSUS_BLOCK - 1) / CENSUS_BLOCK;
+    const int blocks = (int)std::min<uint64_t>(want, (uint64_t)cus * per_cu);
+    if (filtered)
+        hipLaunchKernelGGL(k_census_filtered, dim3(blocks), dim3(CENSUS_BLOCK), lds, st, a);
+    else
+        hipLaunchKernelGGL(k_census_lanes, dim3(blocks), dim3(CENSUS_BLOCK), lds, st, a);
     return hipGetLastError();
 }
 

@@ -142,7 +142,7 @@ struct GenArgs {                    // write matrices first .. first+count-1 as 
 
 constexpr int CENSUS_LANE_MAX_N = 20;   // one matrix per lane up to this n
 
-hipError_t launch_census_lanes(const CensusArgs &a, int grid_blocks, hipStream_t st);
+hipError_t launch_census_lanes(const CensusArgs &a, int cus, hipStream_t st);
 hipError_t launch_generate(const GenArgs &a, hipStream_t st);
 
 }  // namespace perm3

@@ -831,9 +831,7 @@ int32_t perm_mod3_census(int32_t n, int32_t generator, uint64_t key, uint64_t fi
         a.first = first;
         a.count = count;
         a.counts = dcounts;
-        const uint64_t want = (count + 255) / 256;
-        const int blocks = (int)std::min<uint64_t>(want, (uint64_t)c->cus * 8);
-        HIP_TRY(launch_census_lanes(a, blocks, st));
+        HIP_TRY(launch_census_lanes(a, c->cus, st));
     } else {
         // generate chunks into device memory and walk them as a batch; the
         // histogram row 3n..3n+2 accumulates the results

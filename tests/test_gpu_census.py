@@ -43,6 +43,24 @@ def test_random_matrices_vs_oracle():
         assert P.perm_mod3_census(n, SPLIT, 5 + n, 0, cnt) == oracle.census(n, 1, 5 + n, 0, cnt), n
 
 
+def test_random_matrices_every_lane_order_vs_oracle():
+    """Every order the lanes walk: up to 8 with every index tested, from 9 on through the
+    block filter and the wave's re-walk lists; counts over thousands of matrices."""
+    sizes = {3: 20000, 4: 20000, 6: 20000, 7: 20000, 8: 20000, 9: 20000, 10: 20000,
+             12: 8000, 13: 4000, 15: 1500, 16: 800, 18: 200, 19: 120}
+    for n, cnt in sizes.items():
+        assert P.perm_mod3_census(n, SPLIT, 300 + n, 17, cnt) == oracle.census(n, 1, 300 + n, 17, cnt), n
+
+
+def test_single_matrices_vs_oracle():
+    """One matrix per call, so each count is that matrix's own perm mod 3."""
+    for n in (8, 9, 10, 14, 17, 20):
+        for t in (0, 1, 5, 1000003):
+            got = P.perm_mod3_census(n, SPLIT, 9000 + n, t, 1)
+            assert sum(got) == 1
+            assert got == oracle.census(n, 1, 9000 + n, t, 1), (n, t)
+
+
 def test_exact_z5_table3():
     """All 3^25 = 847,288,609,443 matrices 5 x 5 over F_3, walked on the device."""
     z = z_table()
