@@ -94,3 +94,24 @@ def test_sparse40_structured():
     Z = W.sparse_matrix(40, g)
     Z[:, 7] = 0
     assert P.perm_mod3_range_tally(Z, 0, 1 << 40) == 0
+
+
+@pytest.mark.parametrize("n", [38, 40])
+def test_multilinear_in_a_row(n):
+    """perm is linear in each row: with A and A2 equal but for row r, and A3 equal to them but
+    with row r the entrywise sum of theirs over F_3, perm(A) + perm(A2) = perm(A3) mod 3.  Three
+    independent whole-range walks per case, four cases per n, rows r spread over the low, middle
+    and high Gray bits; and perm(A) = perm(A with row r replaced by its negation) * 2."""
+    g = W.rng(900 + n)
+    for r in (0, 5, n // 2, n - 1):
+        flush_print(f"multilinearity n={n} row={r}")
+        A = g.integers(0, 3, size=(n, n), dtype=np.uint8)
+        A2 = A.copy()
+        A2[r] = g.integers(0, 3, size=n, dtype=np.uint8)
+        A3 = A.copy()
+        A3[r] = (A[r].astype(np.int32) + A2[r]) % 3
+        p, p2, p3 = P.perm_mod3(A), P.perm_mod3(A2), P.perm_mod3(A3)
+        assert (p + p2) % 3 == p3, (n, r, p, p2, p3)
+        N = A.copy()
+        N[r] = (3 - N[r].astype(np.int32)) % 3
+        assert P.perm_mod3(N) == (2 * p) % 3, (n, r)
