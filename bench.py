@@ -733,6 +733,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-baselines", action="store_true",
                     help="skip the one-launch-per-matrix and FIFO baselines (for profiling)")
+    ap.add_argument("--no-default-tuning", action="store_true",
+                    help="skip the second run of the headline and the batch with the built-in tuning "
+                         "(so that a kernel trace holds only the tuned launches)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one device-to-device copy of this many MiB (a known-size kernel for "
                          "calibrating the FETCH_SIZE / WRITE_SIZE counters)")
@@ -778,8 +781,8 @@ def main():
         line["roofline"]["tuning_source"] = tune["source"]
         line["headline_detail"] = {k: v for k, v in h.items() if k != "roofline"}
         line["headline_detail"]["tuning"] = tune
-        hd = with_default_tuning(P, P.PERM_TUNE_LARGE,
-                                 lambda: bench_headline(P, W, torch, max(5, args.steps // 2), args.warmup))
+        hd = None if args.no_default_tuning else with_default_tuning(
+            P, P.PERM_TUNE_LARGE, lambda: bench_headline(P, W, torch, max(5, args.steps // 2), args.warmup))
         if hd is not None:
             line["headline_default_tuning"] = {
                 "terms_per_s": hd["terms_per_s"], "hot_kernel_ms_mean": hd["hot_kernel_ms_mean"],
@@ -798,8 +801,8 @@ def main():
         bt["tuning"] = tune
         log(f"batch: {bt['matrices_per_s']:.1f} matrices/s ({bt.get('speedup_vs_baseline', 0):.1f}x one-launch, "
             f"tuning: {tune['source']})")
-        bd = with_default_tuning(P, P.PERM_TUNE_BATCH,
-                                 lambda: bench_batch(P, W, torch, reps=max(3, args.steps // 4), baseline=False))
+        bd = None if args.no_default_tuning else with_default_tuning(
+            P, P.PERM_TUNE_BATCH, lambda: bench_batch(P, W, torch, reps=max(3, args.steps // 4), baseline=False))
         if bd is not None:
             bt["default_tuning"] = {"matrices_per_s": bd["matrices_per_s"], "terms_per_s": bd["terms_per_s"],
                                     "ms_per_batch": bd["ms_per_batch"],
