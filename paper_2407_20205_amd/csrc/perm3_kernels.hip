@@ -47,7 +47,8 @@ __device__ __forceinline__ int walk_lane(RP R, int n, int m, int mode, uint64_t 
     const uint64_t e = e0 < hi ? e0 : hi;
     if (a >= e) return 0;
     if (a == a0 && e == e0) {
-        if (mode == MODE_FAST) return walk_chunks_fast<UL, 1, DEFER>(R, n, m, c, mk, sr);
+        // the closing row read a block ahead pays in the one-matrix walk only
+        if (mode == MODE_FAST) return walk_chunks_fast<UL, 1, DEFER, !DEFER>(R, n, m, c, mk, sr);
         return n > 32 ? walk_chunk_direct<true>(R, n, m, c, mk) : walk_chunk_direct<false>(R, n, m, c, mk);
     }
     return n > 32 ? walk_range_direct<true>(R, n, a, e, mk) : walk_range_direct<false>(R, n, a, e, mk);
@@ -66,7 +67,7 @@ __device__ __forceinline__ int walk_lane_states(RP R, int n, int m, int mode, ui
             const uint64_t a0 = (c + 64u * (uint64_t)q) << m;
             whole &= a0 >= lo && a0 + (1ull << m) <= hi;
         }
-        if (whole) return walk_chunks_fast<UL, S, DEFER>(R, n, m, c, masks_for(n), sr);
+        if (whole) return walk_chunks_fast<UL, S, DEFER, !DEFER>(R, n, m, c, masks_for(n), sr);
     }
     int tally = 0;
 #pragma unroll

@@ -362,9 +362,17 @@ PERM3_FN int flush_candidates(RP R, int n, int m, I c, const MK &mk, const uint3
 // at once by the whole wave, backwards from its end state (rewalk_back), so
 // the block keeps no copy of the state it started from.
 //
+// AHEAD: the row of the step closing a block is loaded one block ahead, so
+// that its load has a whole block to land; else at the block's start, where
+// the wave waits for it.  Which is faster depends on how the register
+// allocator then lays out the rest (loaded ahead in every walk, the
+// one-matrix walk ran 2.7% faster but the batch walk 2.8% and the
+// 128-column walk 10% slower), so the caller picks: the one-matrix walk
+// reads ahead, the others keep their code.
+//
 // The chunk index c is a uint64_t for n <= 63 and a u128 for wider matrices
 // (with MasksX); only the seed and the exact terms see its high bits.
-template <int UL, int S, bool DEFER, typename RP, typename I, typename MK>
+template <int UL, int S, bool DEFER, bool AHEAD, typename RP, typename I, typename MK>
 PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const StaticRows<UL> &sr)
 {
     static_assert(S == 1 || S == 2 || S == 4, "1, 2 or 4 states per lane");
@@ -389,16 +397,34 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const Stati
     const uint32_t lane_tag = (uint32_t)PERM3_LANE() << 26;
     uint32_t ncand = 0;
     const uint32_t half = 1u << (m - UL - 1);
+    // The row added by the step into block j of a half ending at bend (a zero
+    // row when j = bend; t = UL + ctz(j) <= m < n is in range even unused).
+    auto closing_row = [&](uint32_t j, uint32_t bend, uint32_t &rm, uint32_t &rs) {
+        const bool in = j < bend;
+        const int t = UL + __builtin_ctz(j);
+        const bool leave = (j >> (t + 1 - UL)) & 1u;
+        rm = in ? R[t].m_lo : 0u;
+        rs = in ? (leave ? R[t].sn_lo : R[t].s_lo) : 0u;
+    };
     for (uint32_t h = 0; h < 2; ++h) {
         const uint32_t bend = (h + 1) * half;
+        uint32_t next_m = 0, next_s = 0;
+        if (AHEAD) closing_row(h * half + 1, bend, next_m, next_s);
         for (uint32_t b = h * half; b < bend; ++b) {
             // boundary step into block b+1 when it lies in this half (t < m-1)
             const uint32_t jb = b + 1;
             const bool inner = jb < bend;
-            const int tb = UL + __builtin_ctz(jb);      // <= m < n: in range even when unused
-            const bool leave = (jb >> (tb + 1 - UL)) & 1u;
-            const uint32_t bm = PERM3_TO_VGPR(inner ? R[tb].m_lo : 0u);
-            const uint32_t bs = PERM3_TO_VGPR(inner ? (leave ? R[tb].sn_lo : R[tb].s_lo) : 0u);
+            uint32_t bm, bs;
+            if (AHEAD) {
+                bm = PERM3_TO_VGPR(next_m);
+                bs = PERM3_TO_VGPR(next_s);
+                closing_row(jb + 1, bend, next_m, next_s);
+            } else {
+                const int tb = UL + __builtin_ctz(jb);      // <= m < n: in range even when unused
+                const bool leave = (jb >> (tb + 1 - UL)) & 1u;
+                bm = PERM3_TO_VGPR(inner ? R[tb].m_lo : 0u);
+                bs = PERM3_TO_VGPR(inner ? (leave ? R[tb].sn_lo : R[tb].s_lo) : 0u);
+            }
             uint32_t acc = 0;
 #pragma unroll
             for (int k = 1; k <= (int)U; ++k) {
@@ -498,7 +524,7 @@ PERM3_FN int walk_lane_wide(RP R, int n, int m, bool fast, u128 c0, uint64_t off
     const uint64_t oa = oa0 > off_lo ? oa0 : off_lo;
     const uint64_t oe = oe0 < off_hi ? oe0 : off_hi;
     if (oa >= oe) return 0;
-    if (fast && oa == oa0 && oe == oe0) return walk_chunks_fast<UL, 1, DEFER>(R, n, m, c0 + cr, mk, sr);
+    if (fast && oa == oa0 && oe == oe0) return walk_chunks_fast<UL, 1, DEFER, false>(R, n, m, c0 + cr, mk, sr);
     const u128 base = c0 << m;
     const u128 ia = base + oa;
     uint32_t ml, sl;

@@ -142,10 +142,12 @@ static long long chunks_ul_s(const RowW *R, int n, int m, uint64_t c)
 {
     StaticRows<UL> sr;
     load_static_rows<UL>(R, sr);
-    // both ways of re-walking candidate blocks: noted and re-walked after the chunk, or at once
-    const long long deferred = walk_chunks_fast<UL, S, true>(R, n, m, c, masks_of(n), sr);
-    const long long direct = walk_chunks_fast<UL, S, false>(R, n, m, c, masks_of(n), sr);
-    if (deferred != direct) {
+    // both ways of re-walking candidate blocks (noted and re-walked after the
+    // chunk, or at once) and both times of reading a block's closing row
+    const long long deferred = walk_chunks_fast<UL, S, true, false>(R, n, m, c, masks_of(n), sr);
+    const long long direct = walk_chunks_fast<UL, S, false, false>(R, n, m, c, masks_of(n), sr);
+    const long long ahead = walk_chunks_fast<UL, S, false, true>(R, n, m, c, masks_of(n), sr);
+    if (deferred != direct || ahead != direct) {
         printf("error\n");
         exit(1);
     }
