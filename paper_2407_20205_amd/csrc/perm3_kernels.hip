@@ -35,8 +35,9 @@ __device__ __forceinline__ Masks masks_for(int n)
     return mk;
 }
 
-// Walk one lane's chunk c (chunk length 2^m) clipped to [lo, hi).
-template <int UL, bool DEFER, typename RP>
+// Walk one lane's chunk c (chunk length 2^m) clipped to [lo, hi).  DEFER and
+// AHEAD choose the fast walk's form (walk_chunks_fast).
+template <int UL, bool DEFER, bool AHEAD, typename RP>
 __device__ __forceinline__ int walk_lane(RP R, int n, int m, int mode, uint64_t c,
                                          uint64_t lo, uint64_t hi, const StaticRows<UL> &sr)
 {
@@ -47,8 +48,7 @@ __device__ __forceinline__ int walk_lane(RP R, int n, int m, int mode, uint64_t 
     const uint64_t e = e0 < hi ? e0 : hi;
     if (a >= e) return 0;
     if (a == a0 && e == e0) {
-        // the closing row read a block ahead pays in the one-matrix walk only
-        if (mode == MODE_FAST) return walk_chunks_fast<UL, 1, DEFER, !DEFER>(R, n, m, c, mk, sr);
+        if (mode == MODE_FAST) return walk_chunks_fast<UL, 1, DEFER, AHEAD>(R, n, m, c, mk, sr);
         return n > 32 ? walk_chunk_direct<true>(R, n, m, c, mk) : walk_chunk_direct<false>(R, n, m, c, mk);
     }
     return n > 32 ? walk_range_direct<true>(R, n, a, e, mk) : walk_range_direct<false>(R, n, a, e, mk);
@@ -56,7 +56,7 @@ __device__ __forceinline__ int walk_lane(RP R, int n, int m, int mode, uint64_t 
 
 // Walk a lane's S chunks c + 64 s, s = 0 .. S-1, clipped to [lo, hi): side by
 // side when all are whole fast-mode chunks, else one after another.
-template <int UL, int S, bool DEFER, typename RP>
+template <int UL, int S, bool DEFER, bool AHEAD, typename RP>
 __device__ __forceinline__ int walk_lane_states(RP R, int n, int m, int mode, uint64_t c,
                                                 uint64_t lo, uint64_t hi, const StaticRows<UL> &sr)
 {
@@ -67,11 +67,12 @@ __device__ __forceinline__ int walk_lane_states(RP R, int n, int m, int mode, ui
             const uint64_t a0 = (c + 64u * (uint64_t)q) << m;
             whole &= a0 >= lo && a0 + (1ull << m) <= hi;
         }
-        if (whole) return walk_chunks_fast<UL, S, DEFER, !DEFER>(R, n, m, c, masks_for(n), sr);
+        if (whole) return walk_chunks_fast<UL, S, DEFER, AHEAD>(R, n, m, c, masks_for(n), sr);
     }
     int tally = 0;
 #pragma unroll
-    for (int q = 0; q < S; ++q) tally += walk_lane<UL, DEFER>(R, n, m, mode, c + 64u * (uint64_t)q, lo, hi, sr);
+    for (int q = 0; q < S; ++q)
+        tally += walk_lane<UL, DEFER, AHEAD>(R, n, m, mode, c + 64u * (uint64_t)q, lo, hi, sr);
     return tally;
 }
 
@@ -425,13 +426,14 @@ __device__ void pack_small_planes(const PlanArgs &a, const PackPlanesArgs &pp, i
 // ------------------------------------------------------------------ walk
 
 // One task of one matrix: the lane's S chunks, with the matrix's block length;
-// candidate blocks re-walked together after each chunk (DEFER) or each at once.
-template <int UL, int S, bool DEFER, typename RP>
+// candidate blocks re-walked together after each chunk (DEFER) or each at once;
+// each block's closing row read a block ahead (AHEAD) or at its start.
+template <int UL, int S, bool DEFER, bool AHEAD, typename RP>
 __device__ __forceinline__ int walk_task(RP R, const MatMeta &mt, uint64_t c)
 {
     StaticRows<UL> sr;
     if (mt.mode == MODE_FAST) load_static_rows<UL>(R, sr);
-    return walk_lane_states<UL, S, DEFER>(R, mt.n, mt.m, mt.mode, c, mt.lo, mt.hi, sr);
+    return walk_lane_states<UL, S, DEFER, AHEAD>(R, mt.n, mt.m, mt.mode, c, mt.lo, mt.hi, sr);
 }
 
 // DEFER: candidate blocks noted and re-walked one lane each (batches, whose
@@ -472,11 +474,11 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
             const cptr<RowW> R = to_const(a.rows) + mt.row_base;
             const uint64_t c = mt.c_first + q * (64u * S) + (uint64_t)lane;
             if (mt.ul == 4)
-                tally = walk_task<4, S, DEFER>(R, mt, c);
+                tally = walk_task<4, S, DEFER, true>(R, mt, c);
             else if (mt.ul == 6)
-                tally = walk_task<6, S, DEFER>(R, mt, c);
+                tally = walk_task<6, S, DEFER, true>(R, mt, c);
             else
-                tally = walk_task<5, S, DEFER>(R, mt, c);
+                tally = walk_task<5, S, DEFER, true>(R, mt, c);
         }
         const int sum = wave_sum(tally);
 
@@ -657,11 +659,11 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk,
         if (!bad) {
             const uint64_t c = m.c_first + q * 64u + (uint64_t)lane;
             if (m.ul == 4)
-                tally = walk_task<4, 1, true>(R, m, c);
+                tally = walk_task<4, 1, true, false>(R, m, c);
             else if (m.ul == 6)
-                tally = walk_task<6, 1, true>(R, m, c);
+                tally = walk_task<6, 1, true, false>(R, m, c);
             else
-                tally = walk_task<5, 1, true>(R, m, c);
+                tally = walk_task<5, 1, true, false>(R, m, c);
         }
         const int sum = wave_sum(tally);
         if (lane == 0) {
@@ -718,11 +720,11 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_tick(TickArgs a)
         if (lane < tk.nchunks) {
             const uint64_t c = tk.c_first + (uint64_t)lane;
             if (tk.ul == 4)
-                tally = walk_task<4, 1, true>(R, mt, c);
+                tally = walk_task<4, 1, true, false>(R, mt, c);
             else if (tk.ul == 6)
-                tally = walk_task<6, 1, true>(R, mt, c);
+                tally = walk_task<6, 1, true, false>(R, mt, c);
             else
-                tally = walk_task<5, 1, true>(R, mt, c);
+                tally = walk_task<5, 1, true, false>(R, mt, c);
         }
         const int sum = wave_sum(tally);
         if (lane == 0 && sum != 0)

@@ -365,10 +365,10 @@ PERM3_FN int flush_candidates(RP R, int n, int m, I c, const MK &mk, const uint3
 // AHEAD: the row of the step closing a block is loaded one block ahead, so
 // that its load has a whole block to land; else at the block's start, where
 // the wave waits for it.  Which is faster depends on how the register
-// allocator then lays out the rest (loaded ahead in every walk, the
-// one-matrix walk ran 2.7% faster but the batch walk 2.8% and the
-// 128-column walk 10% slower), so the caller picks: the one-matrix walk
-// reads ahead, the others keep their code.
+// allocator then lays out the rest, so the caller picks: the persistent walk
+// reads ahead (one matrix 2.7% faster; a batch 2.2% faster once re-tuned, 2.8%
+// slower under its old tuning), the one-launch small calls, the serving
+// ticks and the 128-column walk (10% slower reading ahead) keep their code.
 //
 // The chunk index c is a uint64_t for n <= 63 and a u128 for wider matrices
 // (with MasksX); only the seed and the exact terms see its high bits.
