@@ -720,11 +720,11 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_tick(TickArgs a)
         if (lane < tk.nchunks) {
             const uint64_t c = tk.c_first + (uint64_t)lane;
             if (tk.ul == 4)
-                tally = walk_task<4, 1, true, false>(R, mt, c);
+                tally = walk_task<4, 1, true, true>(R, mt, c);
             else if (tk.ul == 6)
-                tally = walk_task<6, 1, true, false>(R, mt, c);
+                tally = walk_task<6, 1, true, true>(R, mt, c);
             else
-                tally = walk_task<5, 1, true, false>(R, mt, c);
+                tally = walk_task<5, 1, true, true>(R, mt, c);
         }
         const int sum = wave_sum(tally);
         if (lane == 0 && sum != 0)

@@ -367,8 +367,9 @@ PERM3_FN int flush_candidates(RP R, int n, int m, I c, const MK &mk, const uint3
 // the wave waits for it.  Which is faster depends on how the register
 // allocator then lays out the rest, so the caller picks: the persistent walk
 // reads ahead (one matrix 2.7% faster; a batch 2.2% faster once re-tuned, 2.8%
-// slower under its old tuning), the one-launch small calls, the serving
-// ticks and the 128-column walk (10% slower reading ahead) keep their code.
+// slower under its old tuning) and so do the serving ticks (p99 6% lower);
+// the one-launch small calls and the 128-column walk (10% slower reading
+// ahead) keep their code.
 //
 // The chunk index c is a uint64_t for n <= 63 and a u128 for wider matrices
 // (with MasksX); only the seed and the exact terms see its high bits.
