@@ -367,9 +367,10 @@ PERM3_FN int flush_candidates(RP R, int n, int m, I c, const MK &mk, const uint3
 // the wave waits for it.  Which is faster depends on how the register
 // allocator then lays out the rest, so the caller picks: the persistent walk
 // reads ahead (one matrix 2.7% faster; a batch 2.2% faster once re-tuned, 2.8%
-// slower under its old tuning) and so do the serving ticks (p99 6% lower);
-// the one-launch small calls and the 128-column walk (10% slower reading
-// ahead) keep their code.
+// slower under its old tuning), so do the serving ticks (p99 6% lower) and the
+// 128-column walk, there together with the deferred re-walks (8.5% faster on
+// uniform matrices; either change alone made it slower); the one-launch small
+// calls keep their code.
 //
 // The chunk index c is a uint64_t for n <= 63 and a u128 for wider matrices
 // (with MasksX); only the seed and the exact terms see its high bits.
@@ -516,7 +517,7 @@ PERM3_FN MasksX masks_wide(int n)
 // 2^128.  A whole chunk of a fast-mode matrix takes the unrolled walk; a
 // ragged end (or a small matrix) is seeded at its first index and tests every
 // index on the low word, forming the other words only where it passes.
-template <int UL, bool DEFER, typename RP>
+template <int UL, bool DEFER, bool AHEAD, typename RP>
 PERM3_FN int walk_lane_wide(RP R, int n, int m, bool fast, u128 c0, uint64_t off_lo, uint64_t off_hi,
                             uint64_t cr, const MasksX &mk, const StaticRows<UL> &sr)
 {
@@ -525,7 +526,7 @@ PERM3_FN int walk_lane_wide(RP R, int n, int m, bool fast, u128 c0, uint64_t off
     const uint64_t oa = oa0 > off_lo ? oa0 : off_lo;
     const uint64_t oe = oe0 < off_hi ? oe0 : off_hi;
     if (oa >= oe) return 0;
-    if (fast && oa == oa0 && oe == oe0) return walk_chunks_fast<UL, 1, DEFER, false>(R, n, m, c0 + cr, mk, sr);
+    if (fast && oa == oa0 && oe == oe0) return walk_chunks_fast<UL, 1, DEFER, AHEAD>(R, n, m, c0 + cr, mk, sr);
     const u128 base = c0 << m;
     const u128 ia = base + oa;
     uint32_t ml, sl;

@@ -176,8 +176,11 @@ static long long wide_ul(const RowX *R, int n, int m, bool fast, u128 c0, uint64
 {
     StaticRows<UL> sr;
     load_static_rows<UL>(R, sr);
-    const long long deferred = walk_lane_wide<UL, true>(R, n, m, fast, c0, off_lo, off_hi, cr, masks_wide(n), sr);
-    const long long direct = walk_lane_wide<UL, false>(R, n, m, fast, c0, off_lo, off_hi, cr, masks_wide(n), sr);
+    // the kernel's form (deferred re-walks, rows read ahead) against the plain one
+    const long long deferred =
+        walk_lane_wide<UL, true, true>(R, n, m, fast, c0, off_lo, off_hi, cr, masks_wide(n), sr);
+    const long long direct =
+        walk_lane_wide<UL, false, false>(R, n, m, fast, c0, off_lo, off_hi, cr, masks_wide(n), sr);
     if (deferred != direct) {
         printf("error\n");
         exit(1);
