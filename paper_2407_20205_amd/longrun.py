@@ -33,6 +33,9 @@ def shard_bounds(n: int, shards: int, k: int) -> tuple[int, int]:
 
 
 def _save(path: str, state: dict) -> None:
+    d = os.path.dirname(path)
+    if d:
+        os.makedirs(d, exist_ok=True)
     tmp = path + ".tmp"
     with open(tmp, "w") as f:
         json.dump(state, f)

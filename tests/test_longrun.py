@@ -94,3 +94,15 @@ def test_shard_bounds_cover_the_range():
         pts = [longrun.shard_bounds(n, s, k) for k in range(s)]
         assert pts[0][0] == 0 and pts[-1][1] == 1 << n
         assert all(pts[k][1] == pts[k + 1][0] for k in range(s - 1))
+
+
+def test_checkpoint_directory_is_made(tmp_path):
+    A = W.uniform_matrix(10, 64)
+    ck = str(tmp_path / "not" / "yet" / "ck.json")
+    tallies = longrun.sharded_tallies(A, 4, tally_fn=oracle.range_tally, checkpoint=ck)
+    assert sum(tallies) == oracle.range_tally(A, 0, 1 << 10)
+
+    def never(*args):
+        raise AssertionError("a resumed run walked a shard again")
+
+    assert longrun.sharded_tallies(A, 4, tally_fn=never, checkpoint=ck) == tallies
