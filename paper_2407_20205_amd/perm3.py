@@ -8,6 +8,7 @@ torch is used only to hand over device memory and streams.
 from __future__ import annotations
 
 import ctypes
+import functools
 import os
 from typing import Sequence
 
@@ -252,6 +253,7 @@ def perm_mod3_from_tallies(n: int, tallies) -> int:
 # is therefore checked here, before any C call: dtype, contiguity, length and
 # device, in that order.
 
+@functools.lru_cache(maxsize=None)
 def _dtypes(*names):
     import torch
     return tuple(getattr(torch, k) for k in names if hasattr(torch, k))
