@@ -474,9 +474,191 @@ __global__ void __launch_bounds__(256) k_generate(GenArgs a)
     a.ns[idx] = n;
 }
 
+// ---------------------------------------------------------------- enumeration, 27 matrices a lane
+
+// Enumerated matrices come in groups of 27: matrices 27 g .. 27 g + 26 share
+// every base-3 digit but their three lowest (entries 0, 1 and 2 of row 0),
+// which run through all 27 combinations.  So a lane holds a group
+// bit-sliced: bit q of a word belongs to matrix 27 g + q, entry k of all 27
+// is one (mag, sgn) word pair (a fixed pattern for k < 3, all ones or all
+// zeros from digit k - 3 of g otherwise), and each column sum of the Gray
+// walk is one word pair as well.  A Gray step adds or subtracts one row to
+// the n column sums (n Theorem 2.1 operations), a term needs every column
+// sum non-zero (an AND over the n mag words) and its sign is the parity of
+// the negative ones (an XOR over the n sgn words) and of the index, and the
+// 27 tallies mod 3 are kept as one more word pair.  One step costs about 4n
+// word operations for 27 matrices.
+constexpr int SLICE = 27;
+constexpr uint32_t SLICE_MASK = (1u << SLICE) - 1u;
+
+// mag and sgn patterns of base-3 digit r (r < 3) over q = 0 .. 26
+__host__ __device__ constexpr uint32_t slice_pattern(int r, bool sgn)
+{
+    uint32_t w = 0;
+    for (int q = 0; q < SLICE; ++q) {
+        const int d = (r == 0 ? q : (r == 1 ? q / 3 : q / 9)) % 3;
+        if (sgn ? d == 2 : d != 0) w |= 1u << q;
+    }
+    return w;
+}
+
+// Theorem 2.1 subtraction in three 3-input ops: x = m1 & (s1 ^ s2),
+// mag = x | (m1 ^ m2), sgn = x ^ m2 ^ s2.
+constexpr uint32_t TT_A_AND_BXC = (0xF0 & (0xCC ^ 0xAA)) & 0xFF;
+constexpr uint32_t TT_A_OR_BXC = (0xF0 | (0xCC ^ 0xAA)) & 0xFF;
+__device__ __forceinline__ void f3_sub(uint32_t &m1, uint32_t &s1, uint32_t m2, uint32_t s2)
+{
+    const uint32_t x = PERM3_BITOP3(m1, s1, s2, TT_A_AND_BXC);
+    const uint32_t mo = PERM3_BITOP3(x, m1, m2, TT_A_OR_BXC);
+    s1 = PERM3_BITOP3(x, m2, s2, TT_XOR3);
+    m1 = mo;
+}
+
+constexpr uint32_t TT_AND3 = (0xF0 & 0xCC & 0xAA) & 0xFF;
+
+// k_census_lanes for the enumeration generator (n = N <= 6), a group of 27
+// matrices per lane step: counts of perm = 0, 1, 2 over matrices
+// first .. first + count - 1.
+template <int N>
+__global__ void __launch_bounds__(CENSUS_BLOCK) k_census_sliced(CensusArgs a)
+{
+    constexpr int NN = N * N;
+    constexpr int ND = NN > 3 ? NN - 3 : 0;     // digits of the group number g
+    const int lane = threadIdx.x & 63;
+    const uint64_t g_first = a.first / SLICE;
+    const uint64_t g_last = (a.first + a.count - 1) / SLICE;
+    const uint64_t groups = g_last - g_first + 1;
+    const uint64_t lanes = (uint64_t)gridDim.x * CENSUS_BLOCK;
+    const uint64_t per = (groups + lanes - 1) / lanes;
+    const uint64_t g0 = g_first + ((uint64_t)blockIdx.x * CENSUS_BLOCK + threadIdx.x) * per;
+    const uint64_t g1 = g0 + per < g_last + 1 ? g0 + per : g_last + 1;
+    unsigned long long c0 = 0, c1 = 0, c2 = 0;
+    // digit d of g as bit d of dm (digit != 0) and of ds (digit == 2)
+    uint64_t dm = 0, ds = 0;
+    {
+        uint64_t rest = g0;
+        for (int d = 0; d < ND; ++d) {
+            const uint64_t q = rest / 3u;
+            const uint32_t v = (uint32_t)(rest - 3u * q);
+            rest = q;
+            dm |= (uint64_t)(v != 0) << d;
+            ds |= (uint64_t)(v == 2) << d;
+        }
+    }
+    for (uint64_t g = g0; g < g1; ++g) {
+        // entry words: k < 3 a fixed pattern, else all ones or zeros from digit k - 3
+        uint32_t em[NN], es[NN];
+#pragma unroll
+        for (int k = 0; k < NN; ++k) {
+            if (k < 3) {
+                em[k] = slice_pattern(k, false);
+                es[k] = slice_pattern(k, true);
+            } else {
+                const int d = k - 3;
+                const uint32_t wm = (uint32_t)(dm >> (d & 32)), ws = (uint32_t)(ds >> (d & 32));
+                em[k] = (uint32_t)(-(int32_t)((wm >> (d & 31)) & 1u));
+                es[k] = (uint32_t)(-(int32_t)((ws >> (d & 31)) & 1u));
+            }
+        }
+        // the Gray walk over all 2^N subsets of rows from the empty one; the
+        // column sums start at zero and index 0's term is 0
+        uint32_t cm[N], cs[N];
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+            cm[j] = 0;
+            cs[j] = 0;
+        }
+        uint32_t tm = 0, ts = 0;
+#pragma unroll
+        for (int i = 1; i < (1 << N); ++i) {
+            const int t = __builtin_ctz(i);
+            const bool leave = (i >> (t + 1)) & 1;    // row t leaves the subset
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                if (leave)
+                    f3_sub(cm[j], cs[j], em[t * N + j], es[t * N + j]);
+                else
+                    bip_add(cm[j], cs[j], em[t * N + j], es[t * N + j]);
+            }
+            // every column sum non-zero, and the parity of the negative ones
+            uint32_t hit = cm[0], sx = cs[0];
+            int j = 1;
+#pragma unroll
+            for (; j + 1 < N; j += 2) {
+                hit = PERM3_BITOP3(hit, cm[j], cm[j + 1], TT_AND3);
+                sx = PERM3_BITOP3(sx, cs[j], cs[j + 1], TT_XOR3);
+            }
+            if (j < N) {
+                hit &= cm[j];
+                sx ^= cs[j];
+            }
+            // the term is (-1)^(negative sums + i): add it to the tallies mod 3
+            const uint32_t neg = (i & 1) ? ~sx : sx;
+            bip_add(tm, ts, hit, hit & neg);
+        }
+        // perm = (-1)^N T; the valid matrices of the group
+        const uint64_t base = g * SLICE;
+        const uint64_t lo = a.first > base ? a.first - base : 0;
+        const uint64_t end = a.first + a.count;
+        const uint64_t hi = end < base + SLICE ? end - base : SLICE;
+        const uint32_t valid = (uint32_t)(((1ull << hi) - 1ull) & ~((1ull << lo) - 1ull));
+        const uint32_t minus = (N & 1) ? (tm & ~ts) : (tm & ts);
+        c0 += (unsigned long long)__builtin_popcount(valid & ~tm);
+        c2 += (unsigned long long)__builtin_popcount(valid & minus);
+        c1 += (unsigned long long)__builtin_popcount(valid & tm & ~minus);
+        // g + 1: digits 2 roll over to 0 up to the first digit below 2, which grows
+        const uint64_t twos = dm & ds;
+        const int c = __builtin_ctzll(~twos);
+        const uint64_t below = c >= 64 ? ~0ull : ((1ull << c) - 1ull);
+        dm &= ~below;
+        ds &= ~below;
+        if (c < 64) {
+            const uint64_t bit = 1ull << c;
+            if (dm & bit)
+                ds |= bit;
+            else
+                dm |= bit;
+        }
+    }
+    // the wave's counts to its first lane, then one atomic each
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        c0 += (unsigned long long)__shfl_xor((long long)c0, off);
+        c1 += (unsigned long long)__shfl_xor((long long)c1, off);
+        c2 += (unsigned long long)__shfl_xor((long long)c2, off);
+    }
+    if (lane == 0) {
+        if (c0) atomicAdd(&a.counts[0], c0);
+        if (c1) atomicAdd(&a.counts[1], c1);
+        if (c2) atomicAdd(&a.counts[2], c2);
+    }
+}
+
 hipError_t launch_census_lanes(const CensusArgs &a, int cus, hipStream_t st)
 {
     if (a.n < 1 || a.n > CENSUS_LANE_MAX_N) return hipErrorInvalidValue;
+    if (a.gen == GEN_ENUMERATE) {
+        if (a.n > 6) return hipErrorInvalidValue;
+        const void *ks[6] = {(const void *)k_census_sliced<1>, (const void *)k_census_sliced<2>,
+                             (const void *)k_census_sliced<3>, (const void *)k_census_sliced<4>,
+                             (const void *)k_census_sliced<5>, (const void *)k_census_sliced<6>};
+        int per_cu = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, ks[a.n - 1], CENSUS_BLOCK, 0);
+        if (e != hipSuccess) return e;
+        if (per_cu < 1) per_cu = 1;
+        const uint64_t groups = (a.first + a.count - 1) / SLICE - a.first / SLICE + 1;
+        const uint64_t want = (groups + CENSUS_BLOCK - 1) / CENSUS_BLOCK;
+        const int blocks = (int)std::min<uint64_t>(want, (uint64_t)cus * per_cu);
+        switch (a.n) {
+        case 1: hipLaunchKernelGGL(k_census_sliced<1>, dim3(blocks), dim3(CENSUS_BLOCK), 0, st, a); break;
+        case 2: hipLaunchKernelGGL(k_census_sliced<2>, dim3(blocks), dim3(CENSUS_BLOCK), 0, st, a); break;
+        case 3: hipLaunchKernelGGL(k_census_sliced<3>, dim3(blocks), dim3(CENSUS_BLOCK), 0, st, a); break;
+        case 4: hipLaunchKernelGGL(k_census_sliced<4>, dim3(blocks), dim3(CENSUS_BLOCK), 0, st, a); break;
+        case 5: hipLaunchKernelGGL(k_census_sliced<5>, dim3(blocks), dim3(CENSUS_BLOCK), 0, st, a); break;
+        default: hipLaunchKernelGGL(k_census_sliced<6>, dim3(blocks), dim3(CENSUS_BLOCK), 0, st, a); break;
+        }
+        return hipGetLastError();
+    }
     const bool filtered = a.gen == GEN_SPLITMIX && a.n >= CENSUS_FILTER_MIN_N;
     const int rows = filtered ? a.n - CENSUS_UL : a.n;
     const size_t lds = 2u * (size_t)rows * CENSUS_BLOCK * sizeof(uint32_t);   // at most 32 KiB

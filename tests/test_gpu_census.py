@@ -34,6 +34,21 @@ def test_enumeration_n5_ranges_vs_oracle():
         assert P.perm_mod3_census(5, ENUM, 0, a, cnt) == oracle.census(5, 0, 0, a, cnt), a
 
 
+def test_enumeration_ranges_every_order_vs_oracle():
+    """Enumeration is walked 27 consecutive matrices a lane: ranges that start and end inside a
+    group of 27, single matrices, one group exactly, ranges up to the last matrix, every n."""
+    for n in range(1, 7):
+        total = 3 ** (n * n)
+        ranges = [(0, min(total, 1)), (0, min(total, 27)), (min(total - 1, 26), 1)]
+        if total > 100:
+            ranges += [(5, 50), (27 * 11 + 13, 40), (total // 2 + 7, min(20000, total // 3)),
+                       (total - 61, 61), (total - 27, 27)]
+        for a, cnt in ranges:
+            got = P.perm_mod3_census(n, ENUM, 0, a, cnt)
+            assert sum(got) == cnt
+            assert got == oracle.census(n, 0, 0, a, cnt), (n, a, cnt)
+
+
 def test_random_matrices_vs_oracle():
     for n, cnt in [(1, 1000), (2, 5000), (5, 50000), (8, 50000), (11, 20000), (14, 5000), (17, 600), (20, 100)]:
         assert P.perm_mod3_census(n, SPLIT, 77 + n, 1000, cnt) == oracle.census(n, 1, 77 + n, 1000, cnt), n
