@@ -35,11 +35,12 @@ __device__ __forceinline__ Masks masks_for(int n)
     return mk;
 }
 
-// Walk one lane's chunk c (chunk length 2^m) clipped to [lo, hi).  DEFER and
-// AHEAD choose the fast walk's form (walk_chunks_fast).
+// Walk one lane's chunk c (chunk length 2^m) clipped to [lo, hi): a whole
+// chunk of a fast-mode matrix by walk_chunks_fast (DEFER and AHEAD choose its
+// form), else every index tested exactly.
 template <int UL, bool DEFER, bool AHEAD, typename RP>
 __device__ __forceinline__ int walk_lane(RP R, int n, int m, int mode, uint64_t c,
-                                         uint64_t lo, uint64_t hi, const StaticRows<UL> &sr)
+                                         uint64_t lo, uint64_t hi, const LowSums<UL> &lr)
 {
     const Masks mk = masks_for(n);
     const uint64_t a0 = c << m;
@@ -48,32 +49,10 @@ __device__ __forceinline__ int walk_lane(RP R, int n, int m, int mode, uint64_t 
     const uint64_t e = e0 < hi ? e0 : hi;
     if (a >= e) return 0;
     if (a == a0 && e == e0) {
-        if (mode == MODE_FAST) return walk_chunks_fast<UL, 1, DEFER, AHEAD>(R, n, m, c, mk, sr);
+        if (mode == MODE_FAST) return walk_chunks_fast<UL, DEFER, AHEAD>(R, n, m, c, mk, lr);
         return n > 32 ? walk_chunk_direct<true>(R, n, m, c, mk) : walk_chunk_direct<false>(R, n, m, c, mk);
     }
     return n > 32 ? walk_range_direct<true>(R, n, a, e, mk) : walk_range_direct<false>(R, n, a, e, mk);
-}
-
-// Walk a lane's S chunks c + 64 s, s = 0 .. S-1, clipped to [lo, hi): side by
-// side when all are whole fast-mode chunks, else one after another.
-template <int UL, int S, bool DEFER, bool AHEAD, typename RP>
-__device__ __forceinline__ int walk_lane_states(RP R, int n, int m, int mode, uint64_t c,
-                                                uint64_t lo, uint64_t hi, const StaticRows<UL> &sr)
-{
-    if (S > 1 && mode == MODE_FAST) {
-        bool whole = true;
-#pragma unroll
-        for (int q = 0; q < S; ++q) {
-            const uint64_t a0 = (c + 64u * (uint64_t)q) << m;
-            whole &= a0 >= lo && a0 + (1ull << m) <= hi;
-        }
-        if (whole) return walk_chunks_fast<UL, S, DEFER, AHEAD>(R, n, m, c, masks_for(n), sr);
-    }
-    int tally = 0;
-#pragma unroll
-    for (int q = 0; q < S; ++q)
-        tally += walk_lane<UL, DEFER, AHEAD>(R, n, m, mode, c + 64u * (uint64_t)q, lo, hi, sr);
-    return tally;
 }
 
 // ------------------------------------------------------------------ plan
@@ -425,15 +404,20 @@ __device__ void pack_small_planes(const PlanArgs &a, const PackPlanesArgs &pp, i
 
 // ------------------------------------------------------------------ walk
 
-// One task of one matrix: the lane's S chunks, with the matrix's block length;
-// candidate blocks re-walked together after each chunk (DEFER) or each at once;
-// each block's closing row read a block ahead (AHEAD) or at its start.
-template <int UL, int S, bool DEFER, bool AHEAD, typename RP>
+// One task of one matrix: the lane's S chunks c + 64 s, one after another,
+// in blocks of 2^WALK_UL indices; candidate blocks re-walked together after
+// each chunk (DEFER) or each at once; each block's closing row read a block
+// ahead (AHEAD) or at its start.
+template <int S, bool DEFER, bool AHEAD, typename RP>
 __device__ __forceinline__ int walk_task(RP R, const MatMeta &mt, uint64_t c)
 {
-    StaticRows<UL> sr;
-    if (mt.mode == MODE_FAST) load_static_rows<UL>(R, sr);
-    return walk_lane_states<UL, S, DEFER, AHEAD>(R, mt.n, mt.m, mt.mode, c, mt.lo, mt.hi, sr);
+    LowSums<WALK_UL> lr;
+    if (mt.mode == MODE_FAST) load_low_sums<WALK_UL>(R, lr);
+    int tally = 0;
+#pragma unroll
+    for (int q = 0; q < S; ++q)
+        tally += walk_lane<WALK_UL, DEFER, AHEAD>(R, mt.n, mt.m, mt.mode, c + 64u * (uint64_t)q, mt.lo, mt.hi, lr);
+    return tally;
 }
 
 // DEFER: candidate blocks noted and re-walked one lane each (batches, whose
@@ -473,12 +457,7 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk(WalkArgs a)
         if (to_const(a.status)[k] == 0) {
             const cptr<RowW> R = to_const(a.rows) + mt.row_base;
             const uint64_t c = mt.c_first + q * (64u * S) + (uint64_t)lane;
-            if (mt.ul == 4)
-                tally = walk_task<4, S, DEFER, true>(R, mt, c);
-            else if (mt.ul == 6)
-                tally = walk_task<6, S, DEFER, true>(R, mt, c);
-            else
-                tally = walk_task<5, S, DEFER, true>(R, mt, c);
+            tally = walk_task<S, DEFER, true>(R, mt, c);
         }
         const int sum = wave_sum(tally);
 
@@ -658,12 +637,7 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_small(PlanArgs a, PackU8Args pk,
         int tally = 0;
         if (!bad) {
             const uint64_t c = m.c_first + q * 64u + (uint64_t)lane;
-            if (m.ul == 4)
-                tally = walk_task<4, 1, true, false>(R, m, c);
-            else if (m.ul == 6)
-                tally = walk_task<6, 1, true, false>(R, m, c);
-            else
-                tally = walk_task<5, 1, true, false>(R, m, c);
+            tally = walk_task<1, true, false>(R, m, c);
         }
         const int sum = wave_sum(tally);
         if (lane == 0) {
@@ -719,12 +693,7 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_tick(TickArgs a)
         int tally = 0;
         if (lane < tk.nchunks) {
             const uint64_t c = tk.c_first + (uint64_t)lane;
-            if (tk.ul == 4)
-                tally = walk_task<4, 1, true, true>(R, mt, c);
-            else if (tk.ul == 6)
-                tally = walk_task<6, 1, true, true>(R, mt, c);
-            else
-                tally = walk_task<5, 1, true, true>(R, mt, c);
+            tally = walk_task<1, true, true>(R, mt, c);
         }
         const int sum = wave_sum(tally);
         if (lane == 0 && sum != 0)

@@ -165,23 +165,6 @@ PERM3_FN void seed_lo(RP R, int n, I i0, uint32_t &ml, uint32_t &sl)
     }
 }
 
-// Static rows of the unrolled block: t = 0 .. UL-1, wave-uniform.
-template <int UL>
-struct StaticRows {
-    uint32_t m[UL], s[UL], sn[UL];
-};
-
-template <int UL, typename RP>
-PERM3_FN void load_static_rows(RP R, StaticRows<UL> &sr)
-{
-#pragma unroll
-    for (int t = 0; t < UL; ++t) {
-        sr.m[t] = R[t].m_lo;
-        sr.s[t] = R[t].s_lo;
-        sr.sn[t] = R[t].sn_lo;
-    }
-}
-
 // A wave-uniform word moved into a vector register.  bitop3 with a scalar
 // operand issues more slowly than with three vector operands on gfx950, so
 // the rows the block adds are kept in VGPRs.
@@ -217,38 +200,11 @@ PERM3_FN int rewalk_exact(RP R, int n, I ia, I ib, uint32_t ml, uint32_t sl, con
     return tally;
 }
 
-// Exact re-walk of a block backwards: (ml, sl) is the low-word state at
-// Gray index ib; indices ib, ib-1, .. ia+1 are tested, each step undone by
-// adding back what the step into it removed (or removing what it added).  An
-// undone step may leave a zero as (0,1) where the forward walk had (0,0); the
-// test reads only mag and, where every mag bit is set, sgn, and neither
-// depends on how a zero is represented.
-//
-// All lanes of a wave walk their chunks in step, so within a block every
-// active lane is at the same offset: the flipped row and its direction (a
-// block never contains the chunk's middle step, the only one whose direction
-// differs between lanes) are wave-uniform and the rows come in by scalar
-// loads.
-template <typename RP, typename I, typename MK>
-PERM3_FN int rewalk_back(RP R, int n, I ia, I ib, uint32_t ml, uint32_t sl, const MK &mk)
-{
-    int tally = 0;
-    for (I i = ib; i != ia; --i) {
-        tally += exact_term(R, n, i, ml, sl, mk);
-        const uint32_t il = (uint32_t)i;                 // offsets within a chunk fit 32 bits
-        const int t = PERM3_UNIFORM(__builtin_ctz(il));
-        const bool left = PERM3_UNIFORM((il >> (t + 1)) & 1u);   // the step into i removed row t
-        bip_add(ml, sl, R[t].m_lo, left ? R[t].s_lo : R[t].sn_lo);
-    }
-    return tally;
-}
-
 // Candidate blocks of a wave, re-walked later all together (one lane per
 // block) instead of each by the whole wave at once: an entry holds the lane
-// whose chunk it is (bits 26..31), whether the block ends on a boundary step
-// (bit 25) and the block number (bits 0..24; blocks per chunk are at most
-// 2^(24-4)).  Up to CAND_CAP entries per wave, in LDS; the walk kernels run
-// 4 waves per workgroup.
+// whose chunk it is (bits 26..31) and the block number (bits 0..25; blocks
+// per chunk are at most 2^(24-4)).  Up to CAND_CAP entries per wave, in LDS;
+// the walk kernels run 4 waves per workgroup.
 constexpr uint32_t CAND_CAP = 128;
 constexpr int CAND_WAVES = 4;
 
@@ -275,16 +231,15 @@ PERM3_FN u128 shfl_from(u128 v, int src)
     return ((u128)hi << 64) | lo;
 }
 
-// The exact terms of one candidate block, walked forward from the Gray state
-// at its first index ia (a multiple of U = 2^UL): indices ia+1 .. ia+U-1 and,
-// when the block closes on a boundary step (inner), ia+U.  Lanes re-walk
-// different blocks side by side, all at the same offset k, so the row flipped
-// at k < U is t = ctz(k) for every lane and comes in by a scalar load; its
-// direction is bit t+1 of k, except at t = UL-1 where it is the parity of the
-// lane's block number.  Only the closing step's row depends on the lane
-// (t = UL + ctz(b+1)).
+// The exact terms of indices ia+1 .. ia+U-1 of one candidate block, walked
+// forward from the Gray state at its first index ia (a multiple of
+// U = 2^UL; ia itself is tested by the caller).  Lanes re-walk different
+// blocks side by side, all at the same offset k, so the row flipped at k is
+// t = ctz(k) for every lane and comes in by a scalar load; its direction is
+// bit t+1 of k, except at t = UL-1 where it is bit UL of ia, the parity of
+// the lane's block number b.
 template <int UL, typename RP, typename I, typename MK>
-PERM3_FN int rewalk_block(RP R, int n, I ia, uint32_t b, bool inner, uint32_t ml, uint32_t sl, const MK &mk)
+PERM3_FN int rewalk_block(RP R, int n, I ia, uint32_t b, uint32_t ml, uint32_t sl, const MK &mk)
 {
     constexpr uint32_t U = 1u << UL;
     int tally = 0;
@@ -295,21 +250,87 @@ PERM3_FN int rewalk_block(RP R, int n, I ia, uint32_t b, bool inner, uint32_t ml
         bip_add(ml, sl, R[t].m_lo, leave ? R[t].sn_lo : R[t].s_lo);
         tally += exact_term(R, n, ia + (I)k, ml, sl, mk);
     }
-    if (inner) {
-        const uint32_t jb = b + 1;
-        const int t = UL + __builtin_ctz(jb);
-        const bool leave = ((jb >> (t + 1 - UL)) & 1u) != 0;
-        bip_add(ml, sl, R[t].m_lo, leave ? R[t].sn_lo : R[t].s_lo);
-        tally += exact_term(R, n, ia + (I)U, ml, sl, mk);
-    }
     return tally;
 }
 
-// The exact terms of the candidate blocks a wave noted, list[0 .. ncand):
-// every active lane takes entries in turn, jumps to the Gray state at its
-// block's first index (Section 3.1) and re-walks the block (rewalk_block).
-// A block then costs one lane instead of the whole wave.
-template <int UL, int S, typename RP, typename I, typename MK>
+// ------------------------------------------------------------------ fast walk
+//
+// Write an index of an aligned chunk as i = i0 + b 2^UL + k with k < 2^UL.
+// The low UL bits of g(i) are g(k), with bit UL-1 flipped when the block
+// number b is odd, and the bits above are those of g(i >> UL).  So the
+// subset sum at i is H_b + L, where H_b sums the rows UL .. n-1 of g(i) (one
+// sum per block, moved by one Gray step from block to block) and L sums rows
+// 0 .. UL-1 of the low bits.  Flipping bit UL-1 of g(k) gives g of
+// k xor (2^UL - 1), so an odd block meets the same low sums as an even one,
+// in reverse order: every block's states are exactly {H_b + L_k : k < 2^UL},
+// with L_k the sum of the rows of g(k), the same for every block, chunk and
+// lane of a matrix.
+//
+// The states of a block are then independent of each other (no dependency
+// chain through the block), and the candidate test needs only their mag
+// words: by Theorem 2.1 the mag word of H + L_k is (m_L & y) | (m_H ^ m_L)
+// with y = m_H ^ s_H ^ s_L, two 3-input ops per index where a Gray step that
+// must also carry sgn takes three.  A block with a candidate is walked again
+// exactly, index by index in Gray order.
+//
+// Block length: 2^4.  The 2^UL - 1 word pairs L_k stay in vector registers
+// (a scalar operand makes bitop3 issue more slowly, and 62 scalar words
+// spill); with 2^5-index blocks they hold 62 VGPRs and the walk drops to 5
+// waves per SIMD, which made the 36 x 36 walk slower (4.73 against 4.35 ms
+// for 2^4 on one box).  Forming y as u ^ s_L with u = m_H ^ s_H taken once
+// per block saves an op per block but measured 17% slower (4.35 against
+// 3.72 ms): the 3-input form is what the SIMDs issue fastest.
+constexpr int WALK_UL = 4;
+
+// L_k, k < 2^UL: the low words of the sum of rows g(k) (k = 0 is zero),
+// built by a Gray walk over rows 0 .. UL-1 on the scalar unit, each word
+// moved into a vector register as soon as it is formed (held there for the
+// whole task, so the scalar words are never all live at once).
+template <int UL>
+struct LowSums {
+    uint64_t p[1u << UL];   // mag word << 32 | sgn word
+};
+
+// A 64-bit value held in one register pair: an even-aligned pair of VGPRs,
+// its low word in an even register bank and its high word in an odd one.  A
+// 3-input op whose three sources share one bank issues at about half rate on
+// gfx950, and the allocator left to itself put m_H, s_H and a third operand
+// in one bank for 6 of the 44 ops of a block (the 36 x 36 walk 13% slower
+// than with the words spread).  With H = {m_H low, s_H high} and
+// L_k = {s_L low, m_L high}, the op forming y reads m_H and s_H from banks
+// of both parities, and the op forming the mag word reads m_H (even) and
+// m_L (odd): no op of a block can have all its sources in one bank.
+#ifndef PERM3_PIN_PAIR
+#define PERM3_PIN_PAIR(x) asm("" : "+v"(x))
+#endif
+
+template <int UL, typename RP>
+PERM3_FN void load_low_sums(RP R, LowSums<UL> &lr)
+{
+    constexpr uint32_t U = 1u << UL;
+    uint32_t mm = 0, ss = 0;
+    lr.p[0] = 0;
+#pragma unroll
+    for (uint32_t k = 1; k < U; ++k) {
+        const int t = __builtin_ctz(k);
+        const bool leave = ((k >> (t + 1)) & 1u) != 0;
+        const uint32_t rm = R[t].m_lo, rs = leave ? R[t].sn_lo : R[t].s_lo;
+        // Theorem 2.1's addition on wave-uniform words (scalar ALU)
+        const uint32_t x = rm & (mm ^ ss ^ rs);
+        const uint32_t mo = x | (mm ^ rm);
+        ss = x ^ ss;
+        mm = mo;
+        uint64_t pk = ((uint64_t)PERM3_TO_VGPR(mm) << 32) | PERM3_TO_VGPR(ss);
+        PERM3_PIN_PAIR(pk);
+        lr.p[k] = pk;
+    }
+}
+
+// The exact terms of the candidate blocks a wave noted (entries: lane in
+// bits 26..31, block number below), one lane per entry: jump to the Gray
+// state at the block's first index (Section 3.1), test it, and walk the
+// block's other 2^UL - 1 indices (rewalk_block).
+template <int UL, typename RP, typename I, typename MK>
 PERM3_FN int flush_candidates(RP R, int n, int m, I c, const MK &mk, const uint32_t *list, uint32_t ncand)
 {
     constexpr uint32_t U = 1u << UL;
@@ -323,84 +344,55 @@ PERM3_FN int flush_candidates(RP R, int n, int m, I c, const MK &mk, const uint3
         const uint32_t e = j < ncand ? list[j] : 0u;
         const I ce = shfl_from(c, (int)(e >> 26));   // every active lane takes part
         if (j < ncand) {
-            const uint32_t b = e & 0x1FFFFFFu;
-            const bool inner = ((e >> 25) & 1u) != 0;
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                const I ia = ((ce + (I)(64u * q)) << m) + (I)(b * U);
-                uint32_t ml, sl;
-                seed_lo(R, n, ia, ml, sl);
-                tally += rewalk_block<UL>(R, n, ia, b, inner, ml, sl, mk);
-            }
+            const uint32_t b = e & 0x3FFFFFFu;
+            const I ia = (ce << m) + (I)(b * U);
+            uint32_t ml, sl;
+            seed_lo(R, n, ia, ml, sl);
+            tally += exact_term(R, n, ia, ml, sl, mk) + rewalk_block<UL>(R, n, ia, b, ml, sl, mk);
         }
     }
     return tally;
 }
 
-// Fast walk of S whole aligned chunks c + 64 s (s = 0 .. S-1) of length
-// 2^m, m > UL, carried side by side in one lane.
-//
-// Each chunk is cut into nb = 2^(m-UL) blocks of 2^UL indices.  Inside a
-// block the flipped row t = ctz(offset) and its direction are compile-time
-// constants except for the middle step (t = UL-1, direction = parity of the
-// block number), so each index costs the three bitop3 of the addition, with
-// the rows held in vector registers.  The step into the next block flips a
-// row t >= UL chosen at run time; its row and direction are wave-uniform.
-// The one step of a chunk whose direction differs between lanes (t = m-1,
-// entering the second half; the row leaves the subset when the chunk index
-// is odd) sits between the two halves' loops.  The last block of each half
-// adds a zero row instead of a boundary step, which keeps the block body
-// free of branches.  Chunks 64 apart have the same parity, so the S states
-// take exactly the same row operations: S independent dependency chains.
+// Fast walk of the whole aligned chunk c of length 2^m, m > UL, in blocks
+// of 2^UL indices (above).  H starts as the state at the chunk's first index
+// (whose low m-1 Gray bits are zero) and takes the steps between blocks: the
+// row t = UL + ctz(b+1) into block b+1, wave-uniform, and between the two
+// halves the chunk's middle step (row m-1, which leaves the subset when the
+// chunk index is odd, the one step whose direction differs between lanes).
+// The last block of each half adds a zero row instead, which keeps the block
+// body free of branches.
 //
 // Candidates are found a block at a time: with bits >= n of every row zero,
 // each low mag word is <= mk.lo, so the block's maximum equals mk.lo exactly
 // when some index in it has all its low columns non-zero (one 3-input max
-// per two states, or per two steps when S = 1).  Only then is the block
-// walked again exactly: noted in the wave's candidate list and re-walked by
-// one lane after the chunk (flush_candidates), or, when the list is full,
-// at once by the whole wave, backwards from its end state (rewalk_back), so
-// the block keeps no copy of the state it started from.
+// per two states).  Only then is the block walked again exactly: with DEFER
+// noted in the wave's candidate list and re-walked by one lane after the
+// chunk (flush_candidates), or at once when the list is full; without DEFER
+// at once by the whole wave, from H_b plus row UL-1 when b is odd (the state
+// at the block's first index).
 //
 // AHEAD: the row of the step closing a block is loaded one block ahead, so
-// that its load has a whole block to land; else at the block's start, where
-// the wave waits for it.  Which is faster depends on how the register
-// allocator then lays out the rest, so the caller picks: the persistent walk
-// reads ahead (one matrix 2.7% faster; a batch 2.2% faster once re-tuned, 2.8%
-// slower under its old tuning), so do the serving ticks (p99 6% lower) and the
-// 128-column walk, there together with the deferred re-walks (8.5% faster on
-// uniform matrices; either change alone made it slower); the one-launch small
-// calls keep their code.
+// that its load has a whole block to land; else at the block's start.
 //
 // The chunk index c is a uint64_t for n <= 63 and a u128 for wider matrices
 // (with MasksX); only the seed and the exact terms see its high bits.
-template <int UL, int S, bool DEFER, bool AHEAD, typename RP, typename I, typename MK>
-PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const StaticRows<UL> &sr)
+template <int UL, bool DEFER, bool AHEAD, typename RP, typename I, typename MK>
+PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const LowSums<UL> &lr)
 {
-    static_assert(S == 1 || S == 2 || S == 4, "1, 2 or 4 states per lane");
     constexpr uint32_t U = 1u << UL;
-    uint32_t ml[S], sl[S];
-    int tally = 0;
-#pragma unroll
-    for (int q = 0; q < S; ++q) {
-        const I i0 = (c + (I)(64u * q)) << m;
-        seed_lo(R, n, i0, ml[q], sl[q]);
-        tally += exact_term(R, n, i0, ml[q], sl[q], mk);
-    }
-    // static rows as vector registers
-    uint32_t vm[UL], vs[UL], vsn[UL];
-#pragma unroll
-    for (int t = 0; t < UL; ++t) {
-        vm[t] = PERM3_TO_VGPR(sr.m[t]);
-        vs[t] = PERM3_TO_VGPR(sr.s[t]);
-        vsn[t] = PERM3_TO_VGPR(sr.sn[t]);
-    }
+    const I i0 = c << m;
+    uint32_t m0, s0;
+    seed_lo(R, n, i0, m0, s0);
+    uint64_t hp = ((uint64_t)s0 << 32) | m0;   // H as a register pair
+    PERM3_PIN_PAIR(hp);
     uint32_t *const list = DEFER ? PERM3_CAND_LIST() : nullptr;
     const uint32_t lane_tag = (uint32_t)PERM3_LANE() << 26;
     uint32_t ncand = 0;
+    int tally = 0;
     const uint32_t half = 1u << (m - UL - 1);
-    // The row added by the step into block j of a half ending at bend (a zero
-    // row when j = bend; t = UL + ctz(j) <= m < n is in range even unused).
+    // the row added by the step into block j of a half ending at bend (a zero
+    // row when j = bend; t = UL + ctz(j) <= m < n is in range even unused)
     auto closing_row = [&](uint32_t j, uint32_t bend, uint32_t &rm, uint32_t &rs) {
         const bool in = j < bend;
         const int t = UL + __builtin_ctz(j);
@@ -413,88 +405,72 @@ PERM3_FN int walk_chunks_fast(RP R, int n, int m, I c, const MK &mk, const Stati
         uint32_t next_m = 0, next_s = 0;
         if (AHEAD) closing_row(h * half + 1, bend, next_m, next_s);
         for (uint32_t b = h * half; b < bend; ++b) {
-            // boundary step into block b+1 when it lies in this half (t < m-1)
-            const uint32_t jb = b + 1;
-            const bool inner = jb < bend;
             uint32_t bm, bs;
             if (AHEAD) {
                 bm = PERM3_TO_VGPR(next_m);
                 bs = PERM3_TO_VGPR(next_s);
-                closing_row(jb + 1, bend, next_m, next_s);
+                closing_row(b + 2, bend, next_m, next_s);
             } else {
-                const int tb = UL + __builtin_ctz(jb);      // <= m < n: in range even when unused
-                const bool leave = (jb >> (tb + 1 - UL)) & 1u;
-                bm = PERM3_TO_VGPR(inner ? R[tb].m_lo : 0u);
-                bs = PERM3_TO_VGPR(inner ? (leave ? R[tb].sn_lo : R[tb].s_lo) : 0u);
-            }
-            uint32_t acc = 0;
-#pragma unroll
-            for (int k = 1; k <= (int)U; ++k) {
                 uint32_t rm, rs;
-                if (k < (int)U) {
-                    const int t = __builtin_ctz(k);
-                    rm = vm[t];
-                    if (t < UL - 1)
-                        rs = ((k >> (t + 1)) & 1) ? vsn[t] : vs[t];
-                    else
-                        rs = (b & 1u) ? vsn[t] : vs[t];
-                } else {
-                    rm = bm;
-                    rs = bs;
-                }
+                closing_row(b + 1, bend, rm, rs);
+                bm = PERM3_TO_VGPR(rm);
+                bs = PERM3_TO_VGPR(rs);
+            }
+            uint32_t mh = (uint32_t)hp, sh = (uint32_t)(hp >> 32);
+            // mag words of H + L_k, k = 1 .. U-1 (k = 0 is H itself), folded
+            // by 3-input maxima
+            auto mag_of = [&](uint32_t k) {
+                const uint32_t sl = (uint32_t)lr.p[k], ml = (uint32_t)(lr.p[k] >> 32);
+                return PERM3_BITOP3(PERM3_BITOP3(mh, sh, sl, TT_XOR3), mh, ml, TT_AC_OR_BXC);
+            };
+            uint32_t acc = mh;
 #pragma unroll
-                for (int q = 0; q < S; ++q) bip_add(ml[q], sl[q], rm, rs);
-                if (S == 1) {
-                    acc = k == 1 ? ml[0] : (acc > ml[0] ? acc : ml[0]);
+            for (uint32_t k = 1; k < U; k += 2) {
+                const uint32_t a0 = mag_of(k);
+                if (k + 1 < U) {
+                    const uint32_t a1 = mag_of(k + 1);
+                    const uint32_t x = acc > a0 ? acc : a0;
+                    acc = x > a1 ? x : a1;
                 } else {
-                    // max(max(acc, a), b): one v_max3_u32 per pair of states
-#pragma unroll
-                    for (int q = 0; q < S; q += 2) {
-                        const uint32_t x = acc > ml[q] ? acc : ml[q];
-                        acc = x > ml[q + 1] ? x : ml[q + 1];
-                    }
+                    acc = acc > a0 ? acc : a0;
                 }
             }
             const bool cand = acc == mk.lo;
-            if (!DEFER) {
-                if (cand) {
-                    const uint32_t last = b * U + U - (inner ? 0u : 1u);
-#pragma unroll
-                    for (int q = 0; q < S; ++q) {
-                        const I i0 = (c + (I)(64u * q)) << m;
-                        tally += rewalk_back(R, n, i0 + b * U, i0 + last, ml[q], sl[q], mk);
+            bool now = false;
+            if (DEFER) {
+                const uint64_t cands = PERM3_BALLOT(cand);
+                if (cands) {
+                    const uint32_t nc = (uint32_t)__builtin_popcountll(cands);
+                    if (ncand + nc <= CAND_CAP) {
+                        if (cand) list[ncand + PERM3_RANK(cands)] = lane_tag | b;
+                        ncand += nc;
+                    } else {
+                        now = cand;
                     }
                 }
-                continue;
+            } else {
+                now = cand;
             }
-            const uint64_t cands = PERM3_BALLOT(cand);
-            if (cands) {
-                const uint32_t nc = (uint32_t)__builtin_popcountll(cands);
-                if (ncand + nc <= CAND_CAP) {
-                    if (cand) list[ncand + PERM3_RANK(cands)] = lane_tag | (inner ? 1u << 25 : 0u) | b;
-                    ncand += nc;
-                } else if (cand) {
-                    const uint32_t last = b * U + U - (inner ? 0u : 1u);
-#pragma unroll
-                    for (int q = 0; q < S; ++q) {
-                        const I i0 = (c + (I)(64u * q)) << m;
-                        tally += rewalk_back(R, n, i0 + b * U, i0 + last, ml[q], sl[q], mk);
-                    }
-                }
+            if (now) {
+                const I ia = i0 + (I)(b * U);
+                uint32_t ml = mh, sl = sh;
+                if (b & 1u) bip_add(ml, sl, R[UL - 1].m_lo, R[UL - 1].s_lo);
+                tally += exact_term(R, n, ia, ml, sl, mk) + rewalk_block<UL>(R, n, ia, b, ml, sl, mk);
             }
+            bip_add(mh, sh, bm, bs);
+            hp = ((uint64_t)sh << 32) | mh;
+            PERM3_PIN_PAIR(hp);
         }
         if (h == 0) {
             // offset L/2 flips row m-1
             const bool odd = (c & 1u) != 0;
-            const uint32_t rm = R[m - 1].m_lo, rs = odd ? R[m - 1].sn_lo : R[m - 1].s_lo;
-#pragma unroll
-            for (int q = 0; q < S; ++q) {
-                bip_add(ml[q], sl[q], rm, rs);
-                tally += exact_term(R, n, ((c + (I)(64u * q)) << m) + (I)((uint64_t)half << UL), ml[q], sl[q], mk);
-            }
+            uint32_t mh = (uint32_t)hp, sh = (uint32_t)(hp >> 32);
+            bip_add(mh, sh, R[m - 1].m_lo, odd ? R[m - 1].sn_lo : R[m - 1].s_lo);
+            hp = ((uint64_t)sh << 32) | mh;
+            PERM3_PIN_PAIR(hp);
         }
     }
-    if (DEFER && ncand) tally += flush_candidates<UL, S>(R, n, m, c, mk, list, ncand);
+    if (DEFER && ncand) tally += flush_candidates<UL>(R, n, m, c, mk, list, ncand);
     return tally;
 }
 
@@ -514,19 +490,19 @@ PERM3_FN MasksX masks_wide(int n)
 // One lane's chunk of a range of 128-bit Gray indices.  Chunk cr (counted
 // from c0) covers [B + cr 2^m, B + (cr+1) 2^m) with B = c0 2^m, and the range
 // is [B + off_lo, B + off_hi); offsets stay below 2^64, so a range may end at
-// 2^128.  A whole chunk of a fast-mode matrix takes the unrolled walk; a
+// 2^128.  A whole chunk of a fast-mode matrix takes the fast walk; a
 // ragged end (or a small matrix) is seeded at its first index and tests every
 // index on the low word, forming the other words only where it passes.
 template <int UL, bool DEFER, bool AHEAD, typename RP>
 PERM3_FN int walk_lane_wide(RP R, int n, int m, bool fast, u128 c0, uint64_t off_lo, uint64_t off_hi,
-                            uint64_t cr, const MasksX &mk, const StaticRows<UL> &sr)
+                            uint64_t cr, const MasksX &mk, const LowSums<UL> &lr)
 {
     const uint64_t oa0 = cr << m;
     const uint64_t oe0 = oa0 + (1ull << m);
     const uint64_t oa = oa0 > off_lo ? oa0 : off_lo;
     const uint64_t oe = oe0 < off_hi ? oe0 : off_hi;
     if (oa >= oe) return 0;
-    if (fast && oa == oa0 && oe == oe0) return walk_chunks_fast<UL, 1, DEFER, AHEAD>(R, n, m, c0 + cr, mk, sr);
+    if (fast && oa == oa0 && oe == oe0) return walk_chunks_fast<UL, DEFER, AHEAD>(R, n, m, c0 + cr, mk, lr);
     const u128 base = c0 << m;
     const u128 ia = base + oa;
     uint32_t ml, sl;

@@ -89,17 +89,15 @@ __global__ void __launch_bounds__(128) k_pack_wide(const uint8_t *A, int n, int 
     rows[r] = x;
 }
 
-template <int UL>
 __device__ __forceinline__ int walk_task_wide(cptr<RowX> R, const WideArgs &a, const MasksX &mk, uint64_t cr)
 {
-    StaticRows<UL> sr;
+    LowSums<WALK_UL> lr;
     const bool fast = a.mode == MODE_FAST;
-    if (fast) load_static_rows<UL>(R, sr);
+    if (fast) load_low_sums<WALK_UL>(R, lr);
     const u128 c0 = ((u128)a.c0_hi << 64) | (u128)a.c0_lo;
     // candidate blocks noted and re-walked one lane each after the chunk, and
-    // each block's closing row read a block ahead: together 8.5% faster than
-    // neither on uniform 128 x 128 matrices (each alone was slower)
-    return walk_lane_wide<UL, true, true>(R, a.n, a.m, fast, c0, a.off_lo, a.off_hi, cr, mk, sr);
+    // each block's closing row read a block ahead
+    return walk_lane_wide<WALK_UL, true, true>(R, a.n, a.m, fast, c0, a.off_lo, a.off_hi, cr, mk, lr);
 }
 
 __global__ void __launch_bounds__(WALK_BLOCK) k_walk_wide(WideArgs a)
@@ -110,13 +108,7 @@ __global__ void __launch_bounds__(WALK_BLOCK) k_walk_wide(WideArgs a)
     const MasksX mk = masks_wide(a.n);
     for (uint64_t tau = wave_index(); tau < a.ntasks; tau = next_task64(a.queue, nwaves, lane)) {
         const uint64_t cr = tau * 64u + (uint64_t)lane;
-        int tally;
-        if (a.ul == 4)
-            tally = walk_task_wide<4>(R, a, mk, cr);
-        else if (a.ul == 6)
-            tally = walk_task_wide<6>(R, a, mk, cr);
-        else
-            tally = walk_task_wide<5>(R, a, mk, cr);
+        const int tally = walk_task_wide(R, a, mk, cr);
         const int sum = wave_sum(tally);
         if (lane == 0 && sum != 0) atomicAdd((unsigned long long *)a.tally, (unsigned long long)(long long)sum);
     }

@@ -1,9 +1,9 @@
 """The device walk templates and the planning helpers built for the CPU under AddressSanitizer and
 UndefinedBehaviorSanitizer (tests/walk_cpu.cpp), against the oracle: whole fast-walk chunks for
-every block length and chunks per lane, direct chunks, arbitrary ranges, forward and backward
-re-walks, 128-bit ranges of matrices with up to 128 columns, the plan's cover of a Gray range, and
-the one-launch decision of small calls, whose work sum must not wrap (two orders of 63 add up to
-2^64).  Bar: exact equality."""
+every block length and chunks per lane, direct chunks, arbitrary ranges, forward re-walks and
+whole-block re-walks, 128-bit ranges of matrices with up to 128 columns, the plan's cover of a
+Gray range, and the one-launch decision of small calls, whose work sum must not wrap (two orders
+of 63 add up to 2^64).  Bar: exact equality."""
 import os
 import subprocess
 
@@ -199,7 +199,9 @@ def test_direct_chunks_and_ranges_vs_oracle(harness):
         assert int(line) == oracle.range_tally(A, a, b), (A.shape[0], a, b)
 
 
-def test_forward_and_backward_rewalks_vs_oracle(harness):
+def test_rewalks_vs_oracle(harness):
+    """A forward exact re-walk of a range inside an aligned block, and the exact walk of whole aligned
+    blocks of 2^4, 2^5 and 2^6 indices (one lane's re-walk of a candidate block)."""
     g = W.rng(11)
     cases, want = [], []
     for _ in range(150):
@@ -212,9 +214,14 @@ def test_forward_and_backward_rewalks_vs_oracle(harness):
         cases.append(f"rewalk {n} {a} {e} {digits(A)}")
         want.append((A, a, e + 1))
     for line, (A, a, b) in zip(harness(cases), want):
-        fwd, back = (int(x) for x in line.split())
+        fwd, *blocks = (int(x) for x in line.split())
         w = oracle.range_tally(A, a, b)
-        assert fwd == w and back == w, (A.shape[0], a, b, fwd, back, w)
+        assert fwd == w, (A.shape[0], a, b, fwd, w)
+        n = A.shape[0]
+        for ul, got in zip((4, 5, 6), blocks):
+            if n > ul:
+                lo = a & ~((1 << ul) - 1)
+                assert got == oracle.range_tally(A, lo, lo + (1 << ul)), (n, ul, lo)
 
 
 def test_wide_lanes_vs_oracle(harness):

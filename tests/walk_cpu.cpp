@@ -10,11 +10,13 @@
 //   fused <count> <n_1> .. <n_count>        -> <fused 0/1> <capped work>
 //   target <work> <waves> <tasks_per_wave> <states_log> <queue_task_log> -> target chunk log
 //   plan <n> <lo> <hi> <target_m> <tuning 10 ints> -> <mode> <m> <ul> <c_first> <ntasks>
-//   chunks <UL> <S> <n> <m> <c> <digits>    -> T over chunks c + 64 q, q < S (walk_chunks_fast)
+//   chunks <UL> <S> <n> <m> <c> <digits>    -> T over chunks c + 64 q, q < S (walk_chunks_fast,
+//                                              its four forms checked against each other)
 //   direct <n> <m> <c> <digits>             -> T over chunk c (walk_chunk_direct)
 //   range <n> <a> <e> <digits>              -> T(a, e) (walk_range_direct)
-//   rewalk <n> <a> <b> <digits>             -> T(a, b + 1) by seed + rewalk_exact forward,
-//                                              then by rewalk_back from the state at b
+//   rewalk <n> <a> <b> <digits>             -> T(a, b + 1) by seed + rewalk_exact forward, then
+//                                              T over the aligned blocks of 2^4, 2^5, 2^6
+//                                              holding a (rewalk_block; 0 where n <= UL)
 //   wide <UL> <n> <c0_hi> <c0_lo> <m> <fast> <off_lo> <off_hi> <cr> <digits>
 //                                           -> T of one lane's piece of a 128-bit range
 //
@@ -46,6 +48,7 @@ static inline uint32_t cpu_bitop3(uint32_t a, uint32_t b, uint32_t c, uint32_t t
 #define PERM3_BITOP3(a, b, c, tt) cpu_bitop3((a), (b), (c), (tt))
 #define PERM3_UNIFORM(x) (x)
 #define PERM3_TO_VGPR(x) (x)
+#define PERM3_PIN_PAIR(x) ((void)(x))
 // a wave of one lane
 #define PERM3_BALLOT(p) ((uint64_t)((p) ? 1u : 0u))
 #define PERM3_LANE() 0
@@ -140,14 +143,20 @@ static Masks masks_of(int n)
 template <int UL, int S>
 static long long chunks_ul_s(const RowW *R, int n, int m, uint64_t c)
 {
-    StaticRows<UL> sr;
-    load_static_rows<UL>(R, sr);
-    // both ways of re-walking candidate blocks (noted and re-walked after the
-    // chunk, or at once) and both times of reading a block's closing row
-    const long long deferred = walk_chunks_fast<UL, S, true, false>(R, n, m, c, masks_of(n), sr);
-    const long long direct = walk_chunks_fast<UL, S, false, false>(R, n, m, c, masks_of(n), sr);
-    const long long ahead = walk_chunks_fast<UL, S, false, true>(R, n, m, c, masks_of(n), sr);
-    if (deferred != direct || ahead != direct) {
+    LowSums<UL> lr;
+    load_low_sums<UL>(R, lr);
+    // every form of the fast walk over the chunks c + 64 q, q < S: candidate
+    // blocks noted and re-walked after the chunk or at once, each block's
+    // closing row read a block ahead or at its start
+    long long deferred = 0, direct = 0, ahead = 0, both = 0;
+    for (int q = 0; q < S; ++q) {
+        const uint64_t cq = c + 64u * (uint64_t)q;
+        deferred += walk_chunks_fast<UL, true, false>(R, n, m, cq, masks_of(n), lr);
+        direct += walk_chunks_fast<UL, false, false>(R, n, m, cq, masks_of(n), lr);
+        ahead += walk_chunks_fast<UL, false, true>(R, n, m, cq, masks_of(n), lr);
+        both += walk_chunks_fast<UL, true, true>(R, n, m, cq, masks_of(n), lr);
+    }
+    if (deferred != direct || ahead != direct || both != direct) {
         printf("error\n");
         exit(1);
     }
@@ -174,18 +183,28 @@ template <int UL>
 static long long wide_ul(const RowX *R, int n, int m, bool fast, u128 c0, uint64_t off_lo, uint64_t off_hi,
                          uint64_t cr)
 {
-    StaticRows<UL> sr;
-    load_static_rows<UL>(R, sr);
+    LowSums<UL> lr;
+    load_low_sums<UL>(R, lr);
     // the kernel's form (deferred re-walks, rows read ahead) against the plain one
     const long long deferred =
-        walk_lane_wide<UL, true, true>(R, n, m, fast, c0, off_lo, off_hi, cr, masks_wide(n), sr);
+        walk_lane_wide<UL, true, true>(R, n, m, fast, c0, off_lo, off_hi, cr, masks_wide(n), lr);
     const long long direct =
-        walk_lane_wide<UL, false, false>(R, n, m, fast, c0, off_lo, off_hi, cr, masks_wide(n), sr);
+        walk_lane_wide<UL, false, false>(R, n, m, fast, c0, off_lo, off_hi, cr, masks_wide(n), lr);
     if (deferred != direct) {
         printf("error\n");
         exit(1);
     }
     return deferred;
+}
+
+// The exact terms of the aligned block of 2^UL indices at ia: its first index
+// and rewalk_block over the rest.
+template <int UL>
+static long long block_ul(const RowW *R, int n, uint64_t ia, const Masks &mk)
+{
+    uint32_t ml, sl;
+    seed_lo(R, n, ia, ml, sl);
+    return exact_term(R, n, ia, ml, sl, mk) + rewalk_block<UL>(R, n, ia, (uint32_t)(ia >> UL), ml, sl, mk);
 }
 
 int main()
@@ -249,13 +268,12 @@ int main()
                 uint32_t ml, sl;
                 seed_lo(R, n, (uint64_t)a, ml, sl);
                 const int fwd = exact_term(R, n, (uint64_t)a, ml, sl, mk) + rewalk_exact(R, n, (uint64_t)a, (uint64_t)e, ml, sl, mk);
-                // backward: state at e, then every index e .. a+1 undone, plus the term at a
-                uint32_t mb, sb;
-                seed_lo(R, n, (uint64_t)e, mb, sb);
-                uint32_t ma, sa;
-                seed_lo(R, n, (uint64_t)a, ma, sa);
-                const int back = rewalk_back(R, n, (uint64_t)a, (uint64_t)e, mb, sb, mk) + exact_term(R, n, (uint64_t)a, ma, sa, mk);
-                printf("%d %d\n", fwd, back);
+                // the aligned block of 2^UL around a, UL = 4, 5, 6 (each within range when n > UL)
+                long long blk[3] = {0, 0, 0};
+                if (n > 4) blk[0] = block_ul<4>(R, n, (uint64_t)a & ~15ull, mk);
+                if (n > 5) blk[1] = block_ul<5>(R, n, (uint64_t)a & ~31ull, mk);
+                if (n > 6) blk[2] = block_ul<6>(R, n, (uint64_t)a & ~63ull, mk);
+                printf("%d %lld %lld %lld\n", fwd, blk[0], blk[1], blk[2]);
             }
         } else if (cmd == "wide") {
             int ul, n, m, fast;
