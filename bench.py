@@ -38,10 +38,17 @@ sys.path.insert(0, ROOT)
 # published 157.3 TFLOP/s fp32 vector figure: 157.3e12 / 2 flops / 256 CUs / 2.4 GHz),
 # 256 CUs, 2.4 GHz
 PEAK_LANE_OPS = 256 * 128 * 2.4e9
-# lane-ops the method needs per Gray index on gfx950: three 3-input bitwise ops add
-# one row to the 32-bit low word of the subset sum, and one 3-input max per two
-# indices finds candidates (the high word and the sign only for candidates)
-OPS_PER_TERM = 3.5
+# lane-ops the walk needs per Gray index on gfx950, in blocks of 16 indices whose subset
+# sums are H + L_k (H the block's sum over rows 4 .. n-1, L_k fixed sums of rows 0 .. 3):
+# the 32-bit low mag word of each of the 15 states with k >= 1 in two 3-input bitwise
+# ops, one 3-input max per two of the block's 16 mag words to find candidates, and one
+# Gray step (three 3-input ops) moving H to the next block; the sign and the high word
+# only for candidates
+OPS_PER_TERM = (2 * 15 + 15 / 2 + 3) / 16
+# a chained Gray step's count (three 3-input ops carry mag and sgn of the low word from
+# one index to the next, plus half a max): the walk's count before it was cut into
+# blocks of independent states, reported beside as gray_step_frac
+GRAY_STEP_OPS_PER_TERM = 3.5
 # the paper's count for a two-word (n = 33..64 on 32-bit lanes) step: 6 bitwise ops
 # per word for the add/sub plus one compare per word
 PAPER_OPS_PER_TERM_2W = 14
@@ -166,8 +173,9 @@ def bench_headline(P, W, torch, steps, warmup):
             "traffic": measured_traffic(),
             "ops_per_term": OPS_PER_TERM,
             "terms_per_launch": terms,
-            "kernel": "k_walk<1> (32-step blocks at n = 36)",
+            "kernel": "k_walk<1> (16-index blocks)",
         },
+        "gray_step_frac": GRAY_STEP_OPS_PER_TERM * terms / hot_s / PEAK_LANE_OPS,
         "paper_ops_frac": PAPER_OPS_PER_TERM_2W * terms / hot_s / PEAK_LANE_OPS,
     }
     d = walk_counters()
@@ -233,6 +241,7 @@ def bench_batch(P, W, torch, reps, baseline=True):
                           {"results_differing": bad, "hist_equal": per_n == want_hist})
 
     achieved = OPS_PER_TERM * terms / sec
+    states = int(P.tuning_get_class(P.PERM_TUNE_BATCH)[0].states_per_lane)
     result = {
         "workload": "8192 matrices, n uniform on 12..28, uniform entries, packed (mag, sgn) uint64 planes",
         "matrices_per_s": b.count / sec,
@@ -240,7 +249,8 @@ def bench_batch(P, W, torch, reps, baseline=True):
         # the whole call per batch (plan, pack, walk) by the host clock over graph replays
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "T int32 lane-ops/s", "frac": achieved / PEAK_LANE_OPS, "ops_per_term": OPS_PER_TERM,
-                     "kernel": "k_walk<1, true> (candidate blocks re-walked one lane each)"},
+                     "kernel": f"k_walk<{states}, true> ({states} chunk(s) a lane per task, candidate blocks "
+                               "re-walked one lane each)"},
         "ms_per_batch": 1e3 * sec,
         "hist_per_n": per_n,
         "zero_fraction": float(np.mean(res == 0)),
