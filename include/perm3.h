@@ -345,15 +345,16 @@ int32_t perm_server_destroy(perm_server *s);
  */
 typedef struct {
     int32_t waves_per_simd;   /* persistent waves per SIMD (1..16)                        */
-    int32_t body_log;         /* log2 of the unrolled Gray steps per block, n > mid_max_n:
-                                 4, 5 or 6                                                  */
+    int32_t body_log;         /* n > mid_max_n: a lane's chunk is at least 2^(body_log+1)
+                                 Gray indices and the fast walk takes n >= body_log + 7
+                                 (its blocks are 16 indices whatever the value): 4, 5 or 6  */
     int32_t chunk_log_max;    /* largest per-lane chunk, log2 Gray indices (8..24)        */
     int32_t tasks_per_wave;   /* target tasks per persistent wave                         */
     int32_t direct_max_n;     /* n at or below which every step is tested exactly        */
     int32_t use_graphs;       /* 1: capture device-input calls of more than 64 matrices
                                  into cached HIP graphs                                     */
-    int32_t states_per_lane;  /* chunks a lane walks side by side: 1, 2 or 4              */
-    int32_t body_log_mid;     /* block log2 for direct_max_n < n <= mid_max_n: 4, 5 or 6  */
+    int32_t states_per_lane;  /* chunks a lane walks per task, one after another: 1, 2, 4 */
+    int32_t body_log_mid;     /* body_log for direct_max_n < n <= mid_max_n: 4, 5 or 6    */
     int32_t mid_max_n;        /* see body_log_mid                                         */
     int32_t max_tasks_log;    /* a matrix is cut into at most 2^min(max_tasks_log,
                                  (n-3)/2) tasks ...                                         */
