@@ -4,8 +4,8 @@
 // The decomposition never changes a result, only how the 2^n Gray indices are
 // shared out: the persistent waves per SIMD, the per-lane chunk length (its
 // cap chunk_log_max, the tasks each wave should get, and the bounds on the
-// tasks of one matrix), the unrolled block length, the chunks a lane carries
-// side by side and, for small n, the order at or below which every index is
+// tasks of one matrix), body_log (the shortest chunk), the chunks a lane
+// walks per task and, for small n, the order at or below which every index is
 // tested exactly.  Candidates differ from the class's current tuning in those
 // fields only.  The search is successive halving (Jamieson and Talwalkar,
 // "Non-stochastic best arm identification and hyperparameter optimization",
@@ -44,7 +44,8 @@ double ms_since(Clock::time_point t0)
     return std::chrono::duration<double, std::milli>(Clock::now() - t0).count();
 }
 
-// Set the block length that applies to matrices of order n.
+// Set the body_log (chunks of at least 2^(body_log+1) indices, the fast walk
+// from n = body_log + 7) that applies to matrices of order n.
 void set_block(perm_tuning &t, int n, int bl)
 {
     if (n <= t.mid_max_n) t.body_log_mid = bl; else t.body_log = bl;

@@ -21,7 +21,7 @@
 namespace perm3 {
 
 enum WalkMode : int32_t {
-    MODE_FAST = 0,     // unrolled fast walk over whole chunks, exact replay of candidate blocks
+    MODE_FAST = 0,     // fast walk over whole chunks in blocks of 16, candidate blocks re-walked
     MODE_DIRECT = 1,   // every index tested exactly (small n)
     MODE_NONE = 2,     // no tasks: n == 0, invalid n, or an empty range
 };
@@ -31,7 +31,7 @@ struct MatMeta {
     int32_t n;
     int32_t m;          // log2 of the per-lane chunk length
     int32_t mode;       // WalkMode
-    int32_t ul;         // log2 of the unrolled block (4, 5 or 6)
+    int32_t ul;         // body_log of the matrix's class (4, 5 or 6): chunks of 2^(ul+1) or more
     uint64_t ntasks;    // 64 * S chunks per task
     int64_t row_base;   // first RowW of this matrix
     uint64_t lo, hi;    // Gray index range [lo, hi)
@@ -45,7 +45,7 @@ struct TickTask {
     int32_t mode;         // WalkMode (FAST or DIRECT)
     int32_t nchunks;      // valid chunks in this task (1..64)
     uint64_t c_first;     // first chunk of this task
-    int32_t ul;           // log2 of the unrolled block
+    int32_t ul;           // body_log of the class: chunks of 2^(ul+1) or more
     int32_t pad;
 };
 
@@ -63,7 +63,7 @@ struct PlanArgs {
     int32_t use_range;            // 1: matrix 0 walks [range_lo, range_hi) only (count == 1)
     uint64_t range_lo, range_hi;
     int32_t body_log, chunk_log_max, direct_max_n, direct_chunk_log_max;
-    int32_t body_log_mid, mid_max_n;  // block length for direct_max_n < n <= mid_max_n
+    int32_t body_log_mid, mid_max_n;  // body_log for direct_max_n < n <= mid_max_n
     int32_t states_log;           // log2 of the chunks a lane carries side by side
     int32_t max_tasks_log;        // at most 2^max_tasks_log tasks per matrix ...
     int32_t min_task_log;         // ... unless tasks would exceed 2^min_task_log indices

@@ -12,7 +12,7 @@
 //                that the low word makes a good filter; clears the range's
 //                tally and task counter.
 //   k_walk_wide  persistent waves over 64-chunk tasks of one range; whole
-//                chunks take the unrolled fast walk, ragged ends (and small n)
+//                chunks take the fast walk, ragged ends (and small n)
 //                a walk that tests every index.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
