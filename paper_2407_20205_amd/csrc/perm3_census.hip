@@ -168,14 +168,13 @@ struct CensusCand {
 #define FROW(a, i, who) (a)[((i) - CENSUS_UL) * CENSUS_BLOCK + (who)]
 
 // The exact walk of entries list[0 .. cnt) (cnt <= 64), lane j taking entry j:
-// the 16 indices after 16 b from the saved state, with the rows of the lane
-// the block belongs to (rows 0..3 from that lane's registers, the closing row
-// from LDS), every index tested.  Each entry's tally is added to that lane's
-// word in s_tally.  Every lane of the wave calls it.
-__device__ __forceinline__ void census_flush(uint32_t mask, uint32_t nblocks, int wave_base, int lane,
+// indices 16 b .. 16 b + 15 from the saved state at 16 b, with rows 0..3 of the
+// lane the block belongs to (from that lane's registers), every index tested.
+// Each entry's tally is added to that lane's word in s_tally.  Every lane of
+// the wave calls it.
+__device__ __forceinline__ void census_flush(uint32_t mask, int wave_base, int lane,
                                              const uint32_t (&r_m)[CENSUS_UL], const uint32_t (&r_s)[CENSUS_UL],
-                                             const uint32_t *s_m, const uint32_t *s_s, const CensusCand *list,
-                                             uint32_t cnt, int *s_tally)
+                                             const CensusCand *list, uint32_t cnt, int *s_tally)
 {
     PERM3_WAVE_LDS_SYNC();
     // entries at and above cnt are stale but inside the list: read, never used
@@ -189,45 +188,33 @@ __device__ __forceinline__ void census_flush(uint32_t mask, uint32_t nblocks, in
         vsn[t] = vs[t] ^ vm[t];
     }
     if ((uint32_t)lane < cnt) {
-        const int src = wave_base + src_lane;
         const uint32_t b = e.tag & ((1u << 26) - 1u);
-        const uint32_t jb = b + 1;
-        const bool closing = jb < nblocks;
-        const int tb = closing ? CENSUS_UL + __builtin_ctz(jb) : CENSUS_UL;
-        const bool leave_b = closing && ((jb >> (tb - CENSUS_UL + 1)) & 1u);
-        const uint32_t bm = closing ? FROW(s_m, tb, src) : 0u;
-        const uint32_t bs0 = closing ? FROW(s_s, tb, src) : 0u;
-        const uint32_t bs = leave_b ? (bs0 ^ bm) : bs0;
         uint32_t ml = e.ml, sl = e.sl;
-        int part = 0;
+        // the index 16 b + k has the parity of k
+        int part = ml == mask ? ((__builtin_popcount(sl) & 1) ? -1 : 1) : 0;
 #pragma unroll
-        for (int k = 1; k <= (1 << CENSUS_UL); ++k) {
-            uint32_t rm, rs;
-            if (k < (1 << CENSUS_UL)) {
-                const int t = __builtin_ctz(k);
-                rm = vm[t];
-                const bool leave = t + 1 < CENSUS_UL ? ((k >> (t + 1)) & 1) != 0 : (b & 1u) != 0;
-                rs = leave ? vsn[t] : vs[t];
-            } else {
-                rm = bm;
-                rs = bs;
-            }
-            bip_add(ml, sl, rm, rs);
-            // the index 16 b + k has the parity of k
+        for (int k = 1; k < (1 << CENSUS_UL); ++k) {
+            const int t = __builtin_ctz(k);
+            const bool leave = t + 1 < CENSUS_UL ? ((k >> (t + 1)) & 1) != 0 : (b & 1u) != 0;
+            bip_add(ml, sl, vm[t], leave ? vsn[t] : vs[t]);
             const int odd = (__builtin_popcount(sl) + k) & 1;
-            const bool exists = k < (1 << CENSUS_UL) || closing;
-            part += exists && ml == mask ? (odd ? -1 : 1) : 0;
+            part += ml == mask ? (odd ? -1 : 1) : 0;
         }
-        if (part) atomicAdd(&s_tally[src], part);
+        if (part) atomicAdd(&s_tally[wave_base + src_lane], part);
     }
     PERM3_WAVE_LDS_SYNC();
 }
 
-// The Ryser tally of the lane's matrix for CENSUS_FILTER_MIN_N <= n, found by
-// a filter: the rows have no bit at or above n, so every mag word is at most
-// the mask of n columns and a block of 16 indices holds a non-zero term only
-// if its largest mag word equals the mask.  Such a block is noted (its first
-// Gray state and number) in the wave's list; once 64 are noted, the wave
+// The Ryser tally of the lane's matrix for CENSUS_FILTER_MIN_N <= n, in
+// blocks of 16 Gray indices: the subset sums of block b are H_b + L_k, with
+// H_b the block's sum over rows 4..n-1 (one Gray step from block to block,
+// its row read from LDS one block ahead) and L_k the sums of the lane's rows
+// 0..3 over g(k), the same for every block (an odd block meets them in
+// reverse order).  A block holds a non-zero term only if the largest mag
+// word of its 16 states equals the mask of n columns (the rows have no bit at
+// or above n), and the mag word of H + L_k takes two 3-input ops by Theorem
+// 2.1.  Such a block is noted (the Gray state at its first index: H_b, plus
+// row 3 when b is odd) in the wave's list; once 64 are noted, the wave
 // re-walks them exactly, one per lane, whichever lane's matrix each belongs
 // to.  The lane's tally is left in s_tally[tid] once the wave is through.
 __device__ __forceinline__ void census_walk_filtered(int n, uint32_t mask, int tid, bool active,
@@ -238,17 +225,28 @@ __device__ __forceinline__ void census_walk_filtered(int n, uint32_t mask, int t
     constexpr int U = 1 << CENSUS_UL;
     const int lane = tid & 63;
     const int wave_base = tid & ~63;
-    uint32_t vsn[CENSUS_UL];
+    LowSums<CENSUS_UL> lr;
+    {
+        uint32_t mm = 0, ss = 0;
+        lr.p[0] = 0;
 #pragma unroll
-    for (int t = 0; t < CENSUS_UL; ++t) vsn[t] = r_s[t] ^ r_m[t];
+        for (int k = 1; k < U; ++k) {
+            const int t = __builtin_ctz(k);
+            const bool leave = ((k >> (t + 1)) & 1) != 0;
+            bip_add(mm, ss, r_m[t], leave ? (r_s[t] ^ r_m[t]) : r_s[t]);
+            uint64_t pk = ((uint64_t)mm << 32) | ss;   // {s_L low, m_L high}, as the main walk
+            PERM3_PIN_PAIR(pk);
+            lr.p[k] = pk;
+        }
+    }
     s_tally[tid] = 0;
     const uint32_t nblocks = 1u << (n - CENSUS_UL);
-    uint32_t ml = 0, sl = 0;
+    uint64_t hp = 0;   // H_0: the empty subset
+    PERM3_PIN_PAIR(hp);
     uint32_t ncand = 0;
-    // the row closing a block is read from LDS one block ahead
+    // the row of the step into block b + 1 is read from LDS one block ahead
     uint32_t next_m = FROW(s_m, CENSUS_UL, tid), next_s = FROW(s_s, CENSUS_UL, tid);
     for (uint32_t b = 0; b < nblocks; ++b) {
-        // the step closing block b enters index 16 (b + 1); the last block has none
         const uint32_t jb = b + 1;
         const bool closing = jb < nblocks;
         const int tb = closing ? CENSUS_UL + __builtin_ctz(jb) : CENSUS_UL;
@@ -261,41 +259,37 @@ __device__ __forceinline__ void census_walk_filtered(int n, uint32_t mask, int t
             next_s = FROW(s_s, tn, tid);
         }
         const uint32_t bs = leave_b ? (bs0 ^ bm) : bs0;
-        const uint32_t m0 = ml, s0 = sl;
-        uint32_t acc = 0;
+        uint32_t mh = (uint32_t)hp, sh = (uint32_t)(hp >> 32);
+        uint32_t v[U];
+        v[0] = mh;
 #pragma unroll
-        for (int k = 1; k <= U; ++k) {
-            uint32_t rm, rs;
-            if (k < U) {
-                const int t = __builtin_ctz(k);
-                rm = r_m[t];
-                const bool leave = t + 1 < CENSUS_UL ? ((k >> (t + 1)) & 1) != 0 : (b & 1u) != 0;
-                rs = leave ? vsn[t] : r_s[t];
-            } else {
-                rm = bm;    // the last block adds a zero row: its state stays put
-                rs = bs;
-            }
-            bip_add(ml, sl, rm, rs);
-            acc = acc > ml ? acc : ml;
+        for (int k = 1; k < U; ++k) {
+            const uint32_t sl = (uint32_t)lr.p[k], ml = (uint32_t)(lr.p[k] >> 32);
+            v[k] = PERM3_BITOP3(PERM3_BITOP3(mh, sh, sl, TT_XOR3), mh, ml, TT_AC_OR_BXC);
         }
+        const uint32_t acc = max_tree<U>(v);
         const bool cand = active && acc == mask;
         const uint64_t cands = PERM3_BALLOT(cand);
         if (cands) {
             if (cand) {
                 CensusCand e;
-                e.ml = m0;
-                e.sl = s0;
+                e.ml = mh;
+                e.sl = sh;
+                if (b & 1u) bip_add(e.ml, e.sl, r_m[CENSUS_UL - 1], r_s[CENSUS_UL - 1]);
                 e.tag = ((uint32_t)lane << 26) | b;
                 list[ncand + PERM3_RANK(cands)] = e;
             }
             ncand += (uint32_t)__builtin_popcountll(cands);
             if (ncand >= 64) {
                 ncand -= 64;
-                census_flush(mask, nblocks, wave_base, lane, r_m, r_s, s_m, s_s, list + ncand, 64, s_tally);
+                census_flush(mask, wave_base, lane, r_m, r_s, list + ncand, 64, s_tally);
             }
         }
+        bip_add(mh, sh, bm, bs);   // the last block adds a zero row: H stays put
+        hp = ((uint64_t)sh << 32) | mh;
+        PERM3_PIN_PAIR(hp);
     }
-    if (ncand) census_flush(mask, nblocks, wave_base, lane, r_m, r_s, s_m, s_s, list, ncand, s_tally);
+    if (ncand) census_flush(mask, wave_base, lane, r_m, r_s, list, ncand, s_tally);
 }
 
 // One row of a SplitMix64 matrix, packed by phi (element j at bit n-1-j),
@@ -489,7 +483,6 @@ __global__ void __launch_bounds__(256) k_generate(GenArgs a)
 // 27 tallies mod 3 are kept as one more word pair.  One step costs about 4n
 // word operations for 27 matrices.
 constexpr int SLICE = 27;
-constexpr uint32_t SLICE_MASK = (1u << SLICE) - 1u;
 
 // mag and sgn patterns of base-3 digit r (r < 3) over q = 0 .. 26
 __host__ __device__ constexpr uint32_t slice_pattern(int r, bool sgn)
