@@ -64,7 +64,7 @@ struct PlanArgs {
     uint64_t range_lo, range_hi;
     int32_t body_log, chunk_log_max, direct_max_n, direct_chunk_log_max;
     int32_t body_log_mid, mid_max_n;  // body_log for direct_max_n < n <= mid_max_n
-    int32_t states_log;           // log2 of the chunks a lane carries side by side
+    int32_t states_log;           // log2 of the chunks a lane walks per task
     int32_t max_tasks_log;        // at most 2^max_tasks_log tasks per matrix ...
     int32_t min_task_log;         // ... unless tasks would exceed 2^min_task_log indices
     int32_t queue_task_log;       // floor of a task, once every wave has one that long (0: none)
