@@ -4,7 +4,7 @@ the code objects in libperm3.so are unbundled and disassembled with ROCm's LLVM 
 A 3-input VALU op whose three VGPR sources share one register bank (register number mod 4) issues
 at about half rate on gfx950.  The walk holds its block's high-row sum H and each low-row sum L_k as
 64-bit values pinned to register pairs so that no op of a block can read three sources from one
-bank; left to the allocator, 6 of a block's 44 ops did and the 36x36 walk ran 13% slower.  This
+bank; left to the allocator, 6 of a block's 44 ops did and the 36x36 walk ran 11-13% slower.  This
 test finds every fast-walk block in every walk kernel (a run of code between branches with the
 block's two bitop3 per state and its tree of v_max3) and checks each 3-source op."""
 import os
