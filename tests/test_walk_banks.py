@@ -5,8 +5,9 @@ A 3-input VALU op whose three VGPR sources share one register bank (register num
 at about half rate on gfx950.  The walk holds its block's high-row sum H and each low-row sum L_k as
 64-bit values pinned to register pairs so that no op of a block can read three sources from one
 bank; left to the allocator, 6 of a block's 44 ops did and the 36x36 walk ran 11-13% slower.  This
-test finds every fast-walk block in every walk kernel (a run of code between branches with the
-block's two bitop3 per state and its tree of v_max3) and checks each 3-source op."""
+test finds every fast-walk block in every walk kernel and in the census lanes (a run of code
+between branches with the block's two bitop3 per state and its tree of v_max3) and checks each
+3-source op."""
 import os
 import re
 import shutil
@@ -22,7 +23,11 @@ OBJDUMP = os.path.join(LLVM, "llvm-objdump")
 TARGET = "hipv4-amdgcn-amd-amdhsa--gfx950"
 # the kernels that run the fast walk, by a fragment of their mangled names
 KERNELS = {"k_walk<1, false>": "k_walkILi1ELb0E", "k_walk<2, true>": "k_walkILi2ELb1E",
-           "k_tick": "k_tickENS_8TickArgsE", "k_small": "k_smallENS_8PlanArgs", "k_walk_wide": "k_walk_wideENS"}
+           "k_tick": "k_tickENS_8TickArgsE", "k_small": "k_smallENS_8PlanArgs", "k_walk_wide": "k_walk_wideENS",
+           "k_census_filtered": "k_census_filteredENS"}
+# block loops each kernel holds at least: one per half of a chunk in the chunk walks, one in the
+# census lanes (a lane's whole matrix is one run of blocks)
+MIN_LOOPS = {k: (1 if k == "k_census_filtered" else 2) for k in KERNELS}
 
 
 def code_objects(tmp_path):
@@ -97,5 +102,5 @@ def test_fast_walk_blocks_spread_register_banks(tmp_path):
                 if is_fast_block(run):
                     found[kind] += 1
                     assert not one_bank_ops(run), (kind, one_bank_ops(run))
-    # every walk kernel was looked at: each holds at least one block loop per chunk half
-    assert all(v >= 2 for v in found.values()), found
+    # every walk kernel was looked at
+    assert all(found[k] >= MIN_LOOPS[k] for k in KERNELS), found
